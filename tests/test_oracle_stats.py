@@ -1,0 +1,135 @@
+"""Statistical pins of the CPU oracle against closed forms.
+
+* L = 2 exact enumeration (oracle.enumerate2, computed from eq. 1 alone):
+  serial BKL and the spkMC cycle with R_max over all octants reach the
+  Boltzmann law; the spkMC cycle with R_max over the active octant reaches the
+  closed-form law proportional to sum_s 1/r_s.
+* J = 0: independent spins relax as m(t) = m_inf + (m0 - m_inf) exp(-Gamma t)
+  with m_inf = tanh(beta H); this fixes the time normalisation of step 5.
+* the paper's central claim (Sec. 4): the bias of the parallel method against
+  the serial mean stays within the combined standard deviation (eqs. 6-7).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import enumerate2
+
+TC = 1.0 / 0.2216546
+
+
+def _batch_means(run_batch, nbatch):
+    vals = np.array([run_batch() for _ in range(nbatch)])
+    return vals.mean(axis=0), vals.std(axis=0, ddof=1) / math.sqrt(nbatch)
+
+
+def _tw_batch(sim_or_bkl, n):
+    tw, _ = sim_or_bkl.run_tw(n)
+    return tw[1:] / tw[0]  # <E>, <|M|>, <M^2> time-weighted
+
+
+@pytest.mark.parametrize("T,H,rates", [(TC, 0.0, 0), (3.0, 0.2, 0), (TC, 0.0, 1)])
+def test_l2_bkl_reaches_boltzmann(T, H, rates):
+    ex = enumerate2.averages(1.0, H, T, rates)["boltzmann"]
+    bkl = oracle.Bkl(L=2, T=T, H=H, rates=rates, seed=17)
+    bkl.run(1000)
+    mean, se = _batch_means(lambda: _tw_batch(bkl, 20000), 30)
+    for v, m, s in zip((ex["E"], ex["absM"], ex["M2"]), mean, se):
+        assert abs(m - v) < 5 * s + 1e-9, (m, v, s)
+
+
+@pytest.mark.parametrize("T,H,rates", [(TC, 0.0, 0), (3.0, 0.2, 0), (TC, 0.0, 1)])
+def test_l2_spkmc_active_reaches_closed_form(T, H, rates):
+    laws = enumerate2.averages(1.0, H, T, rates)
+    ex = laws["spkmc_active"]
+    sim = oracle.Sim(L=2, d=2, T=T, H=H, rates=rates, seed=23)
+    sim.run(1000)
+    mean, se = _batch_means(lambda: _tw_batch(sim, 20000), 30)
+    for v, m, s in zip((ex["E"], ex["absM"], ex["M2"]), mean, se):
+        assert abs(m - v) < 5 * s + 1e-9, (m, v, s)
+    # and the test can tell the two laws apart
+    assert abs(laws["boltzmann"]["E"] - ex["E"]) > 20 * se[0]
+
+
+def test_l2_state_distribution():
+    """The whole 256-state time-weighted law, not only three moments."""
+    T, H = TC, 0.1
+    laws = enumerate2.averages(1.0, H, T, 0)
+    for scope, key in ((0, "spkmc_active"), (1, "boltzmann")):
+        sim = oracle.Sim(L=2, d=2, T=T, H=H, seed=31, rmax_scope=scope)
+        _, hist = sim.run_tw(4000000, state_hist=True)
+        p = hist / hist.sum()
+        tv = 0.5 * np.abs(p - laws[key]["p"]).sum()
+        assert tv < 0.01, (scope, tv)
+    # the two laws are far apart compared with that tolerance
+    assert 0.5 * np.abs(laws["spkmc_active"]["p"] - laws["boltzmann"]["p"]).sum() > 0.2
+    bkl = oracle.Bkl(L=2, T=T, H=H, seed=37)
+    _, hist = bkl.run_tw(4000000, state_hist=True)
+    p = hist / hist.sum()
+    assert 0.5 * np.abs(p - laws["boltzmann"]["p"]).sum() < 0.01
+
+
+def test_l2_spkmc_all_octants_reaches_boltzmann():
+    T, H = TC, 0.0
+    ex = enumerate2.averages(1.0, H, T, 0)["boltzmann"]
+    sim = oracle.Sim(L=2, d=2, T=T, H=H, seed=29, rmax_scope=1)
+    sim.run(1000)
+    mean, se = _batch_means(lambda: _tw_batch(sim, 20000), 30)
+    for v, m, s in zip((ex["E"], ex["absM"], ex["M2"]), mean, se):
+        assert abs(m - v) < 5 * s + 1e-9, (m, v, s)
+
+
+def _j0_curve(make, grid, runs):
+    ms = []
+    for r in range(runs):
+        obj = make(r)
+        M, _ = obj.run_grid(grid)
+        assert len(M) == len(grid)
+        ms.append(M / obj.N)
+    return np.array(ms)
+
+
+@pytest.mark.parametrize("rates", [0, 1])
+def test_j0_relaxation_closed_form(rates):
+    """J = 0, field H, from all +1: every spin is an independent two-state
+    process, m(t) = m_inf + (1 - m_inf) exp(-Gamma t) with m_inf = tanh(beta H),
+    Gamma = 1 (Glauber) or 1 + exp(-2 beta |H|) (Metropolis).  A wrong colour
+    factor in the clock would change Gamma eightfold."""
+    T, H = 1.0, 0.3
+    beta = 1.0 / T
+    minf = math.tanh(beta * H)
+    gamma = 1.0 if rates == 0 else 1.0 + math.exp(-2 * beta * abs(H))
+    grid = np.array([0.05, 0.2, 0.5, 1.0, 2.0, 4.0])
+    want = minf + (1 - minf) * np.exp(-gamma * grid)
+    N = 32 ** 3
+    runs = 4
+    sd = np.sqrt((1 - want ** 2) / N / runs)
+    sp = _j0_curve(lambda r: oracle.Sim(L=32, d=16, J=0.0, H=H, T=T, rates=rates, init=1, seed=100 + r),
+                   grid, runs).mean(axis=0)
+    assert np.all(np.abs(sp - want) < 5 * sd + 1e-4), (sp, want)
+    bk = _j0_curve(lambda r: oracle.Bkl(L=32, J=0.0, H=H, T=T, rates=rates, init=1, seed=200 + r),
+                   grid, runs).mean(axis=0)
+    assert np.all(np.abs(bk - want) < 5 * sd + 1e-4), (bk, want)
+
+
+def test_spkmc_bias_within_serial_deviation():
+    """Eqs. 6-7 on the oracle: m(t) from all +1 at T_c, L = 32 (2^15 spins),
+    512 sites per octant; the time-integrated bias of the parallel mean against
+    the serial mean is smaller than 3 sigma_b, sigma_b^2 = sigma_p^2 + sigma_s^2
+    (standard errors of the two means)."""
+    L, d, runs = 32, 16, 12
+    grid = np.linspace(0.5, 8.0, 16)
+
+    def integ(make):
+        vals = []
+        for r in range(runs):
+            M, _ = make(r).run_grid(grid)
+            vals.append(np.trapezoid(M / L ** 3, grid) / (grid[-1] - grid[0]))
+        return np.mean(vals), np.std(vals, ddof=1) / math.sqrt(runs)
+
+    mp, sp = integ(lambda r: oracle.Sim(L=L, d=d, T=TC, init=1, seed=1000 + r))
+    ms, ss = integ(lambda r: oracle.Bkl(L=L, T=TC, init=1, seed=2000 + r))
+    sigma_b = math.sqrt(sp ** 2 + ss ** 2)
+    assert abs(mp - ms) < 3 * sigma_b, (mp, ms, sigma_b)
