@@ -1,0 +1,195 @@
+/*
+ * spkmc.h -- C ABI of the MI355X (gfx950) spkMC library.
+ *
+ * The library runs the synchronous parallel kinetic Monte Carlo cycle of
+ * Martinez, Monasterio and Marian (arXiv:1005.4713) on a periodic L^3 Ising
+ * lattice: Sec. 3.1 steps 1-6 with the sublattice steps 4a/4b of Sec. 3.2, the
+ * energy of eq. 1 and the Glauber rates of eq. 3.  Every step of the cycle runs
+ * in HIP kernels on the GPU; this header exposes plain C types only (no C++,
+ * no torch, no exceptions) so that any caller can drive it.
+ *
+ * Conventions shared by all entry points
+ *   - Lattice: N = L^3 sites, site (x, y, z) has linear index x + L (y + L z),
+ *     periodic boundaries, neighbours counted with multiplicity (at L = 2 the
+ *     +x and -x neighbour coincide and count twice).
+ *   - Domains: edge d (even, d >= 2, L % d == 0), K = (L/d)^3 domains numbered
+ *     kx + (L/d) (ky + (L/d) kz).  Each domain is split into 8 octants of edge
+ *     h = d/2 (the 8-colour chessboard of Sec. 3.2, Fig. 1); colour s in 0..7
+ *     has (sx, sy, sz) = (s & 1, (s >> 1) & 1, (s >> 2) & 1).  Same-colour
+ *     octants are at least h sites apart, so they never interact.
+ *   - Classes: class c = 7 [s_i = +1] + a_i, a_i = number of the 6 neighbours
+ *     aligned with s_i; flip energy change dE_c = 2 J (2 a - 6) + 2 H s_i
+ *     (eq. 1).  Rates (lambda = 1): Glauber r_c = 1 / (1 + exp(beta dE_c))
+ *     (eq. 3 in its detailed-balance form), Metropolis r_c = min(1, exp(-beta dE_c)).
+ *   - One cycle n (Sec. 3.1 / 3.2):
+ *       4a. colour s_n = w0 >> 29 of Philox(ctr = (n_lo, n_hi, ~0, ~0), key = seed);
+ *       1.  R_k = sum_{c=0..13} n_{k,c} r_c over the active octant (k, s_n),
+ *           accumulated in class order with separate FP64 multiply and add;
+ *       2.  R_max = max_k R_k (exact);
+ *       3/4/4b. per domain, u = u53(w0, w1), w = w2 of Philox((n_lo, n_hi, k, s_n));
+ *           target = u R_max; the first class c with target < running sum is
+ *           chosen, none (target >= R_k) is the null event; the flipped site is
+ *           the j-th (j = (w n_c) >> 32) site of class c in canonical order
+ *           q = lx + h (ly + h lz) inside the octant;
+ *       5.  t += -ln(u_t) / (8 R_max), u_t = uopen52(w2, w3) of the cycle draw
+ *           (the 8 makes every spin flip at its physical rate);
+ *       6.  flips become visible to every domain before the next cycle.
+ *     u53(a, b) = ((a >> 5) 2^26 + (b >> 6)) / 2^53;
+ *     uopen52(a, b) = ((((a >> 6) << 26) | (b >> 6)) + 1/2) / 2^52.
+ *   - Initial spins (init = SPKMC_INIT_RANDOM): spin i is bit (i & 31) of word
+ *     ((i >> 5) & 3) of Philox((b_lo, b_hi, 0xFFFFFFFE, 0xFFFFFFFE)), b = i >> 7;
+ *     1 means +1.
+ *   - Memory: the caller owns the device buffer (dev_buf, at least
+ *     spkmc_state_bytes() bytes, 256-byte aligned, on the current HIP device)
+ *     and the HIP stream; the library owns only the host-side context.  No
+ *     entry point allocates device memory after spkmc_init.
+ *   - Asynchrony: spkmc_init and spkmc_run only enqueue work on the stream;
+ *     the other entry points that read device state synchronise the stream.
+ *   - Errors: every call returns a status; spkmc_last_error() explains the
+ *     last failure.  Nothing aborts the process.  A context whose device work
+ *     failed answers SPKMC_E_STATE until destroyed.
+ *   - Threading: one context per stream; calls on one context must not overlap.
+ */
+#ifndef SPKMC_H
+#define SPKMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spkmc_ctx spkmc_ctx;
+
+typedef enum spkmc_status {
+    SPKMC_OK = 0,
+    SPKMC_E_INVAL = 1,       /* invalid parameters or arguments                       */
+    SPKMC_E_NOMEM = 2,       /* host allocation failed                                 */
+    SPKMC_E_DEVICE = 3,      /* a HIP call or a kernel failed                          */
+    SPKMC_E_STATE = 4,       /* context is in a failed state                           */
+    SPKMC_E_RANGE = 5,       /* a buffer is too small                                  */
+    SPKMC_E_UNSUPPORTED = 6  /* the requested engine does not support these parameters */
+} spkmc_status;
+
+enum { SPKMC_RATES_GLAUBER = 0, SPKMC_RATES_METROPOLIS = 1 };
+enum { SPKMC_INIT_RANDOM = 0, SPKMC_INIT_UP = 1, SPKMC_INIT_DOWN = 2 };
+/* Spin storage in the device buffer.  INT8: one byte per site, index x + L (y + L z).
+ * PACKED: one bit per site, octant-major (domain k, colour s, canonical q), plus a
+ * copy of the 6 faces of every octant; needs h % 4 == 0. */
+enum { SPKMC_LAYOUT_INT8 = 0, SPKMC_LAYOUT_PACKED = 1 };
+/* Kernel engine.  AUTO picks PERSISTENT when supported, else CYCLE.
+ * CYCLE: three launches per cycle (bin, select-and-flip, finalize), any layout.
+ * PERSISTENT: one cooperative launch per spkmc_run call with device-wide
+ * barriers between the phases of every cycle (PACKED layout, h = 8 or 16).
+ * Both engines produce bit-identical trajectories. */
+enum { SPKMC_ENGINE_AUTO = 0, SPKMC_ENGINE_CYCLE = 1, SPKMC_ENGINE_PERSISTENT = 2 };
+
+typedef struct spkmc_params {
+    uint32_t struct_size; /* sizeof(spkmc_params): ABI check                           */
+    int32_t L;            /* lattice edge, >= 2                                        */
+    int32_t domain;       /* domain edge d: even, >= 2, L % d == 0                     */
+    int32_t rates;        /* SPKMC_RATES_*                                             */
+    double J;             /* coupling (eq. 1)                                          */
+    double H;             /* external field (eq. 1)                                    */
+    double T;             /* temperature, k_B = 1, > 0                                 */
+    uint64_t seed;        /* Philox key (lo, hi)                                       */
+    int32_t init;         /* SPKMC_INIT_*                                              */
+    int32_t layout;       /* SPKMC_LAYOUT_*                                            */
+    int32_t engine;       /* SPKMC_ENGINE_*                                            */
+    int32_t wg_domains;   /* PERSISTENT: domains per workgroup, 0 = default; other
+                             values change the launch shape, never the results      */
+    uint32_t record_cap;  /* observation records kept on the device (ring)             */
+    uint32_t reserved;    /* must be 0                                                 */
+} spkmc_params;
+
+/* One observation: the state after `cycle` cycles. */
+typedef struct spkmc_record {
+    uint64_t cycle;  /* cycles done                                      */
+    uint64_t fired;  /* non-null events so far                           */
+    uint64_t nulls;  /* null events so far (fired + nulls = K cycle)     */
+    double t;        /* simulated time, units of 1/lambda                */
+    int64_t M;       /* sum_i s_i (eq. 4 times N)                        */
+    int64_t B;       /* sum_i sum_{e = x, y, z} s_i s_{i+e}              */
+} spkmc_record;
+
+typedef struct spkmc_obs {
+    spkmc_record rec; /* current state                                   */
+    double E;         /* -J B - H M (eq. 1)                              */
+    double m;         /* M / N (eq. 4)                                   */
+    double ur;        /* fired / (fired + nulls): utilisation (eq. 8)    */
+} spkmc_obs;
+
+typedef struct spkmc_info {
+    int32_t engine;          /* engine in use (SPKMC_ENGINE_CYCLE or _PERSISTENT) */
+    int32_t layout;          /* layout in use                                    */
+    int32_t h;               /* octant edge                                      */
+    int32_t grid;            /* workgroups of the cycle kernel(s)                */
+    int32_t block;           /* threads per workgroup                            */
+    int32_t wg_domains;      /* domains per workgroup (PERSISTENT)               */
+    uint64_t K;              /* number of domains                                */
+    uint64_t N;              /* number of sites                                  */
+    uint64_t state_bytes;    /* bytes of device state                            */
+    double bytes_per_cycle;  /* algorithmic bytes per cycle: K ((h^3 + 6 h^2)/8 + 8) */
+} spkmc_info;
+
+/* Device bytes needed for these parameters; 0 if the parameters are invalid. */
+size_t spkmc_state_bytes(const spkmc_params *p);
+
+/* Validate p, compute the FP64 rate table on the host, lay out dev_buf and
+ * enqueue the initial state on `hip_stream` (a hipStream_t; NULL = null stream).
+ * *out receives the context (also on some errors, so spkmc_last_error can be
+ * read; destroy it either way).
+ * Errors: E_INVAL (bad parameters: d odd, d < 2, L % d != 0, T <= 0, a rate
+ * that is 0 or not finite, unknown enum, wrong struct_size, reserved != 0,
+ * PACKED with h % 4 != 0), E_RANGE (dev_bytes too small), E_UNSUPPORTED
+ * (engine PERSISTENT with parameters it cannot run), E_DEVICE. */
+spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, void *hip_stream,
+                        spkmc_ctx **out);
+
+/* Enqueue `ncycles` cycles.  Every obs_every cycles (counted by the absolute
+ * cycle number; 0 = never) a record of the state after that cycle is appended
+ * to the device ring of record_cap entries. */
+spkmc_status spkmc_run(spkmc_ctx *ctx, uint64_t ncycles, uint32_t obs_every);
+
+/* Synchronise the stream and return the current state. */
+spkmc_status spkmc_observables(spkmc_ctx *ctx, spkmc_obs *out);
+
+/* Synchronise and copy the most recent min(cap, recorded, record_cap) records,
+ * oldest first, to host memory; *n receives the number copied. */
+spkmc_status spkmc_records(spkmc_ctx *ctx, spkmc_record *host, size_t cap, size_t *n);
+
+/* Synchronise and copy all N spins (+1 / -1, index x + L (y + L z)) to host. */
+spkmc_status spkmc_copy_spins(spkmc_ctx *ctx, int8_t *host, size_t n);
+
+/* Replace all N spins from host memory (values +1 / -1) and recompute M and B;
+ * counters, clock and cycle number are kept.  Synchronises. */
+spkmc_status spkmc_set_spins(spkmc_ctx *ctx, const int8_t *host, size_t n);
+
+/* The 14 FP64 rates c = 0..13 the library uses for these parameters. */
+spkmc_status spkmc_rate_table(const spkmc_params *p, double out[14]);
+
+/* Checkpoint: with host == NULL, *n receives the blob size.  Otherwise the
+ * state (parameters, counters, clock, records, spins) is copied to host
+ * (cap bytes available).  Synchronises. */
+spkmc_status spkmc_save(spkmc_ctx *ctx, void *host, size_t cap, size_t *n);
+
+/* Restore a blob written by spkmc_save for the same parameters.  Resuming is
+ * exact: the random streams are counter-based and keyed by the cycle number. */
+spkmc_status spkmc_load(spkmc_ctx *ctx, const void *host, size_t n);
+
+/* Launch shape and sizes of a context. */
+spkmc_status spkmc_query(const spkmc_ctx *ctx, spkmc_info *out);
+
+/* Message of the last failure on ctx (ctx == NULL: of the last failed call
+ * that had no context on this thread).  Never NULL. */
+const char *spkmc_last_error(const spkmc_ctx *ctx);
+
+/* Free the host context.  Does not free dev_buf or the stream. */
+void spkmc_destroy(spkmc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPKMC_H */

@@ -1,0 +1,305 @@
+// kernels_cycle.hip -- state set-up kernels and the per-cycle ("CYCLE" engine)
+// kernels of the gfx950 spkMC library.
+//
+// One cycle (Sec. 3.1 steps 1-6, Sec. 3.2 steps 4a/4b) is three launches:
+//   k_bin      one workgroup per domain: class histogram of the active octant
+//              (step 1), its FP64 frequency line R_k, device-wide max (step 2);
+//   k_select   one wavefront per domain: draw, frequency-line walk with the
+//              null event last (steps 3, 4, 4b), canonical-order prefix select
+//              of the site with wavefront ballots, flip (step 6 is the kernel
+//              boundary);
+//   k_finalize one thread: clock (step 5), counters, observation record.
+// These kernels are generic over the spin layout and serve as the reference
+// launch shape for the persistent engine.
+#include "spkmc_device.hpp"
+
+namespace spkmc {
+
+// --------------------------------------------------------------------------- set-up
+__global__ void k_init_int8(Geom g, int init) {
+    uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one 128-site block
+    uint64_t first = b << 7;
+    if (first >= g.N) return;
+    U4 w = philox10((uint32_t)b, (uint32_t)(b >> 32), 0xFFFFFFFEu, 0xFFFFFFFEu, g.seed);
+    uint32_t words[4] = {w.x, w.y, w.z, w.w};
+    for (int i = 0; i < 128 && first + i < g.N; ++i) {
+        int v = init == SPKMC_INIT_UP ? 1 : init == SPKMC_INIT_DOWN ? -1 : ((words[i >> 5] >> (i & 31)) & 1u) ? 1 : -1;
+        g.spin8[first + i] = (int8_t)v;
+    }
+}
+
+// One thread per packed word: 32 consecutive canonical sites of one octant.
+__global__ void k_init_packed(Geom g, int init) {
+    uint64_t wi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t total = (uint64_t)g.K * 8 * g.wpo;
+    if (wi >= total) return;
+    uint64_t oct = wi / g.wpo;
+    uint32_t k = (uint32_t)(oct >> 3);
+    int s = (int)(oct & 7);
+    uint32_t q0 = (uint32_t)(wi % g.wpo) * 32;
+    int ox, oy, oz;
+    octant_origin(g, k, s, ox, oy, oz);
+    uint32_t word = 0;
+    if (init == SPKMC_INIT_UP) {
+        word = 0xFFFFFFFFu;
+    } else if (init == SPKMC_INIT_RANDOM) {
+        uint64_t cached = ~0ull;
+        U4 w{0, 0, 0, 0};
+        for (int b = 0; b < 32; ++b) {
+            uint32_t q = q0 + b;
+            int lx = (int)(q % g.h), ly = (int)((q / g.h) % g.h), lz = (int)(q / g.h2);
+            uint64_t i = (uint64_t)(ox + lx) + (uint64_t)g.L * ((uint64_t)(oy + ly) + (uint64_t)g.L * (uint64_t)(oz + lz));
+            uint64_t blk = i >> 7;
+            if (blk != cached) {
+                w = philox10((uint32_t)blk, (uint32_t)(blk >> 32), 0xFFFFFFFEu, 0xFFFFFFFEu, g.seed);
+                cached = blk;
+            }
+            uint32_t src = ((i >> 5) & 3) == 0 ? w.x : ((i >> 5) & 3) == 1 ? w.y : ((i >> 5) & 3) == 2 ? w.z : w.w;
+            word |= ((src >> (i & 31)) & 1u) << b;
+        }
+    }
+    g.A[wi] = word;
+}
+
+// Face copies of every octant, rebuilt from the packed spins.
+// Face f of an octant: x0 (lx = 0), x1 (lx = h-1), y0, y1, z0, z1; inside a face
+// the bit index is (ly + h lz) for x faces, (lx + h lz) for y, (lx + h ly) for z.
+__global__ void k_build_faces(Geom g) {
+    uint64_t fw = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t total = (uint64_t)g.K * 8 * g.fwpo;
+    if (fw >= total) return;
+    uint64_t oct = fw / g.fwpo;
+    uint32_t base_bit = (uint32_t)(fw % g.fwpo) * 32;
+    const uint32_t *octA = g.A + oct * g.wpo;
+    uint32_t word = 0;
+    for (int b = 0; b < 32; ++b) {
+        uint32_t fb = base_bit + b;
+        uint32_t f = fb / g.h2, idx = fb % g.h2;
+        uint32_t u = idx % g.h, v = idx / g.h, e = (f & 1) ? g.h - 1 : 0;
+        uint32_t lx, ly, lz;
+        if (f < 2) { lx = e; ly = u; lz = v; }
+        else if (f < 4) { lx = u; ly = e; lz = v; }
+        else { lx = u; ly = v; lz = e; }
+        uint32_t q = lx + g.h * (ly + g.h * lz);
+        word |= ((octA[q >> 5] >> (q & 31)) & 1u) << b;
+    }
+    g.F[fw] = word;
+}
+
+// M and B of the whole lattice (each bond once: +x, +y, +z of every site).
+template <class S>
+__global__ void k_observables(Geom g) {
+    __shared__ long long shM[256], shB[256];
+    long long m = 0, b = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.N; i += (uint64_t)gridDim.x * blockDim.x) {
+        int x = (int)(i % g.L), y = (int)((i / g.L) % g.L), z = (int)(i / ((uint64_t)g.L * g.L));
+        int s = S::get(g, x, y, z);
+        m += s;
+        b += s * (S::get(g, x + 1 == g.L ? 0 : x + 1, y, z) + S::get(g, x, y + 1 == g.L ? 0 : y + 1, z) +
+                  S::get(g, x, y, z + 1 == g.L ? 0 : z + 1));
+    }
+    shM[threadIdx.x] = m;
+    shB[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            shM[threadIdx.x] += shM[threadIdx.x + o];
+            shB[threadIdx.x] += shB[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&g.st->M, (unsigned long long)shM[0]);
+        atomicAdd((unsigned long long *)&g.st->B, (unsigned long long)shB[0]);
+    }
+}
+
+// --------------------------------------------------------------------------- cycle
+// Step 1 and the device-wide max of step 2.  One workgroup per domain.
+template <class S>
+__global__ void k_bin(Geom g, uint64_t n) {
+    __shared__ uint32_t cnt[16];
+    uint32_t k = blockIdx.x;
+    if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    CycleDraw cd = cycle_draw(g.seed, n);
+    int ox, oy, oz;
+    octant_origin(g, k, cd.colour, ox, oy, oz);
+    for (uint32_t q = threadIdx.x; q < g.h3; q += blockDim.x) {
+        int x = ox + (int)(q % g.h), y = oy + (int)((q / g.h) % g.h), z = oz + (int)(q / g.h2);
+        int s = S::get(g, x, y, z);
+        int c = (s > 0 ? 7 : 0) + aligned_count<S>(g, x, y, z, s);
+        atomicAdd(&cnt[c], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double Rk = line_total(cnt, g.r);
+        g.Rk[k] = Rk;
+        for (int c = 0; c < 16; ++c) g.hist[(uint64_t)k * 16 + c] = c < 14 ? cnt[c] : 0;
+        atomicMax((unsigned long long *)&g.st->rmax[0], (unsigned long long)double_to_bits(Rk));
+    }
+}
+
+// Steps 3, 4, 4b and the flip.  One 64-lane wavefront per domain, four per workgroup.
+template <class S>
+__global__ void __launch_bounds__(256) k_select(Geom g, uint64_t n) {
+    __shared__ long long part[4][3];
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t k = blockIdx.x * 4 + wave;
+    long long fired = 0, dM = 0, dB = 0;
+    if (k < g.K) {
+        CycleDraw cd = cycle_draw(g.seed, n);
+        double Rmax = bits_to_double(g.st->rmax[0]);
+        U4 dw = philox10((uint32_t)n, (uint32_t)(n >> 32), k, (uint32_t)cd.colour, g.seed);
+        double target = unit53(dw.x, dw.y) * Rmax;
+        uint32_t cnt[14];
+        for (int c = 0; c < 14; ++c) cnt[c] = g.hist[(uint64_t)k * 16 + c];
+        int cs = line_select(cnt, g.r, target);
+        if (cs >= 0) {
+            uint32_t j = mul_index(dw.z, cnt[cs]);
+            int ox, oy, oz;
+            octant_origin(g, k, cd.colour, ox, oy, oz);
+            for (uint32_t q0 = 0; q0 < g.h3; q0 += 64) {
+                uint32_t q = q0 + lane;
+                int x = 0, y = 0, z = 0, s = 0, a = 0;
+                bool hit = false;
+                if (q < g.h3) {
+                    x = ox + (int)(q % g.h);
+                    y = oy + (int)((q / g.h) % g.h);
+                    z = oz + (int)(q / g.h2);
+                    s = S::get(g, x, y, z);
+                    a = aligned_count<S>(g, x, y, z, s);
+                    hit = ((s > 0 ? 7 : 0) + a) == cs;
+                }
+                uint64_t m = __ballot(hit);
+                uint32_t c = (uint32_t)__popcll(m);
+                if (j < c) {
+                    // lane whose rank among the hits is j
+                    uint32_t below = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                    if (hit && below == j) {
+                        if (g.layout == SPKMC_LAYOUT_INT8) {
+                            g.spin8[(int64_t)x + (int64_t)g.L * ((int64_t)y + (int64_t)g.L * z)] = (int8_t)(-s);
+                        } else {
+                            uint64_t bit = ((uint64_t)k * 8 + (uint64_t)cd.colour) * g.h3 + q;
+                            atomicXor(&g.A[bit >> 5], 1u << (bit & 31));
+                            uint32_t lx = q % g.h, ly = (q / g.h) % g.h, lz = q / g.h2;
+                            uint32_t *F = g.F + ((uint64_t)k * 8 + (uint64_t)cd.colour) * g.fwpo;
+                            uint32_t e = g.h - 1;
+                            uint32_t fidx[6] = {lx == 0 ? ly + g.h * lz : ~0u, lx == e ? g.h2 + ly + g.h * lz : ~0u,
+                                                ly == 0 ? 2 * g.h2 + lx + g.h * lz : ~0u,
+                                                ly == e ? 3 * g.h2 + lx + g.h * lz : ~0u,
+                                                lz == 0 ? 4 * g.h2 + lx + g.h * ly : ~0u,
+                                                lz == e ? 5 * g.h2 + lx + g.h * ly : ~0u};
+                            for (int f = 0; f < 6; ++f)
+                                if (fidx[f] != ~0u) atomicXor(&F[fidx[f] >> 5], 1u << (fidx[f] & 31));
+                        }
+                        fired = 1;
+                        dM = -2 * s;
+                        dB = 12 - 4 * a;
+                    }
+                    break;
+                }
+                j -= c;
+            }
+        }
+    }
+    // wavefront sums of the one lane that flipped
+    for (int o = 32; o > 0; o >>= 1) {
+        fired += __shfl_xor(fired, o);
+        dM += __shfl_xor(dM, o);
+        dB += __shfl_xor(dB, o);
+    }
+    if (lane == 0) {
+        part[wave][0] = fired;
+        part[wave][1] = dM;
+        part[wave][2] = dB;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long f = 0, m = 0, b = 0;
+        for (int w = 0; w < 4; ++w) {
+            f += part[w][0];
+            m += part[w][1];
+            b += part[w][2];
+        }
+        if (f) atomicAdd((unsigned long long *)&g.st->acc_fired[0], (unsigned long long)f);
+        if (m) atomicAdd((unsigned long long *)&g.st->acc_dM[0], (unsigned long long)m);
+        if (b) atomicAdd((unsigned long long *)&g.st->acc_dB[0], (unsigned long long)b);
+    }
+}
+
+// Step 5 and the bookkeeping of cycle n.
+__global__ void k_finalize(Geom g, uint64_t n, uint32_t obs_every) {
+    if (threadIdx.x != 0) return;
+    DevState *st = g.st;
+    CycleDraw cd = cycle_draw(g.seed, n);
+    double Rmax = bits_to_double(st->rmax[0]);
+    double dt = -log(cd.ut) / (8.0 * Rmax);
+    st->t = st->t + dt;
+    uint64_t f = st->acc_fired[0];
+    st->fired += f;
+    st->nulls += (uint64_t)g.K - f;
+    st->M += st->acc_dM[0];
+    st->B += st->acc_dB[0];
+    st->acc_fired[0] = 0;
+    st->acc_dM[0] = 0;
+    st->acc_dB[0] = 0;
+    st->rmax[0] = 0;
+    st->cycle = n + 1;
+    if (obs_every && ((n + 1) % obs_every) == 0 && g.rec_cap) {
+        spkmc_record r;
+        r.cycle = n + 1;
+        r.fired = st->fired;
+        r.nulls = st->nulls;
+        r.t = st->t;
+        r.M = st->M;
+        r.B = st->B;
+        g.rec[st->rec_count % g.rec_cap] = r;
+        st->rec_count += 1;
+    }
+}
+
+// --------------------------------------------------------------------------- host launchers
+hipError_t launch_init(const Geom &g, int init, hipStream_t stream) {
+    if (g.layout == SPKMC_LAYOUT_INT8) {
+        uint64_t blocks128 = (g.N + 127) / 128;
+        hipLaunchKernelGGL(k_init_int8, dim3((unsigned)((blocks128 + 255) / 256)), dim3(256), 0, stream, g, init);
+    } else {
+        uint64_t words = (uint64_t)g.K * 8 * g.wpo;
+        hipLaunchKernelGGL(k_init_packed, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, stream, g, init);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_faces(const Geom &g, hipStream_t stream) {
+    if (g.layout != SPKMC_LAYOUT_PACKED) return hipSuccess;
+    uint64_t fwords = (uint64_t)g.K * 8 * g.fwpo;
+    hipLaunchKernelGGL(k_build_faces, dim3((unsigned)((fwords + 255) / 256)), dim3(256), 0, stream, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_observables(const Geom &g, hipStream_t stream) {
+    uint64_t blocks = (g.N + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (g.layout == SPKMC_LAYOUT_INT8)
+        hipLaunchKernelGGL(k_observables<Int8Spins>, dim3((unsigned)blocks), dim3(256), 0, stream, g);
+    else
+        hipLaunchKernelGGL(k_observables<PackedSpins>, dim3((unsigned)blocks), dim3(256), 0, stream, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream_t stream) {
+    unsigned bin_block = g.h3 >= 256 ? 256 : 64;
+    unsigned sel_blocks = (g.K + 3) / 4;
+    if (g.layout == SPKMC_LAYOUT_INT8) {
+        hipLaunchKernelGGL(k_bin<Int8Spins>, dim3(g.K), dim3(bin_block), 0, stream, g, n);
+        hipLaunchKernelGGL(k_select<Int8Spins>, dim3(sel_blocks), dim3(256), 0, stream, g, n);
+    } else {
+        hipLaunchKernelGGL(k_bin<PackedSpins>, dim3(g.K), dim3(bin_block), 0, stream, g, n);
+        hipLaunchKernelGGL(k_select<PackedSpins>, dim3(sel_blocks), dim3(256), 0, stream, g, n);
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, stream, g, n, obs_every);
+    return hipGetLastError();
+}
+
+}  // namespace spkmc

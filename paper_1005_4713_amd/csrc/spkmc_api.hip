@@ -1,0 +1,469 @@
+// spkmc_api.hip -- the C ABI declared in include/spkmc.h (host side).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "spkmc_device.hpp"
+
+namespace spkmc {
+hipError_t launch_init(const Geom &g, int init, hipStream_t stream);
+hipError_t launch_faces(const Geom &g, hipStream_t stream);
+hipError_t launch_observables(const Geom &g, hipStream_t stream);
+hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream_t stream);
+bool persistent_supported(const Geom &g, const spkmc_params &p, std::string &why);
+hipError_t persistent_configure(const Geom &g, const spkmc_params &p, int &grid, int &block, int &wg_domains);
+hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid,
+                             int block, int wg_domains, hipStream_t stream);
+}  // namespace spkmc
+
+using namespace spkmc;
+
+struct spkmc_ctx {
+    spkmc_params p;
+    hipStream_t stream;
+    char *dev;
+    size_t dev_bytes;
+    Geom g;
+    size_t spin_off, spin_bytes;   // spin region (A + F, or int8), for save/load
+    size_t rec_off;
+    uint64_t cycle;                // cycles enqueued
+    int engine;
+    int grid, block, wg_domains;
+    bool failed;
+    std::string err;
+};
+
+static thread_local std::string g_last_error = "no error";
+
+static spkmc_status fail(spkmc_ctx *c, spkmc_status st, const std::string &msg) {
+    if (c) {
+        c->err = msg;
+        if (st == SPKMC_E_DEVICE) c->failed = true;
+    } else {
+        g_last_error = msg;
+    }
+    return st;
+}
+
+static spkmc_status hip_fail(spkmc_ctx *c, hipError_t e, const char *where) {
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(c, SPKMC_E_DEVICE, m);
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Host FP64 rate table: class c -> spin sign, aligned count a; flip energy
+// change dE = 2 J (2a - 6) + 2 H s from eq. 1; Glauber 1 / (1 + exp(beta dE))
+// or Metropolis min(1, exp(-beta dE)).  Evaluated without FMA contraction so the
+// values are reproducible bit for bit.
+static int make_rates(const spkmc_params *p, double out[14]) {
+    if (!(p->T > 0.0) || !isfinite(p->T) || !isfinite(p->J) || !isfinite(p->H)) return -1;
+    double beta = 1.0 / p->T;
+    for (int c = 0; c < 14; ++c) {
+        int sgn = c >= 7 ? 1 : -1;
+        int a = c % 7;
+        double dE = 2.0 * p->J * (double)(2 * a - 6) + 2.0 * p->H * (double)sgn;
+        double x = beta * dE;
+        double r = p->rates == SPKMC_RATES_GLAUBER ? 1.0 / (1.0 + exp(x)) : (dE <= 0.0 ? 1.0 : exp(-x));
+        if (!(r > 0.0) || !isfinite(r)) return -2;
+        out[c] = r;
+    }
+    return 0;
+}
+
+struct LayoutPlan {
+    size_t off_rates, off_rec, off_Rk, off_hist, off_flip, off_spin, off_F, total, spin_bytes;
+};
+
+static bool validate(const spkmc_params *p, std::string &why) {
+    if (!p) { why = "params is NULL"; return false; }
+    if (p->struct_size != sizeof(spkmc_params)) { why = "struct_size does not match sizeof(spkmc_params)"; return false; }
+    if (p->reserved != 0) { why = "reserved must be 0"; return false; }
+    if (p->L < 2) { why = "L must be >= 2"; return false; }
+    if (p->domain < 2 || (p->domain & 1)) { why = "domain edge must be even and >= 2"; return false; }
+    if (p->L % p->domain) { why = "L must be a multiple of the domain edge"; return false; }
+    if (p->L > 4096) { why = "L above 4096 is not supported"; return false; }
+    if (p->rates != SPKMC_RATES_GLAUBER && p->rates != SPKMC_RATES_METROPOLIS) { why = "unknown rates"; return false; }
+    if (p->init < 0 || p->init > 2) { why = "unknown init"; return false; }
+    if (p->layout != SPKMC_LAYOUT_INT8 && p->layout != SPKMC_LAYOUT_PACKED) { why = "unknown layout"; return false; }
+    if (p->engine < 0 || p->engine > 2) { why = "unknown engine"; return false; }
+    if (p->wg_domains < 0) { why = "wg_domains must be >= 0"; return false; }
+    int h = p->domain / 2;
+    if (p->layout == SPKMC_LAYOUT_PACKED && (h % 4)) { why = "PACKED layout needs the octant edge (domain/2) to be a multiple of 4"; return false; }
+    double r[14];
+    int rc = make_rates(p, r);
+    if (rc == -1) { why = "T must be > 0 and J, H, T finite"; return false; }
+    if (rc == -2) { why = "a rate is 0 or not finite (temperature too low for FP64)"; return false; }
+    return true;
+}
+
+static LayoutPlan plan(const spkmc_params *p) {
+    LayoutPlan lp;
+    uint64_t L = (uint64_t)p->L, N = L * L * L, nd = L / (uint64_t)p->domain, K = nd * nd * nd;
+    uint64_t h = (uint64_t)p->domain / 2;
+    size_t o = 256;  // DevState
+    lp.off_rates = o; o += 256;
+    lp.off_rec = o; o = align256(o + (size_t)p->record_cap * sizeof(spkmc_record));
+    lp.off_Rk = o; o = align256(o + K * 8);
+    lp.off_hist = o; o = align256(o + K * 64);
+    lp.off_flip = o; o = align256(o + K * 8);
+    lp.off_spin = o;
+    if (p->layout == SPKMC_LAYOUT_INT8) {
+        o = align256(o + N);
+        lp.off_F = 0;
+    } else {
+        o = align256(o + N / 8);
+        lp.off_F = o;
+        o = align256(o + K * 8 * 6 * h * h / 8);
+    }
+    lp.spin_bytes = o - lp.off_spin;
+    lp.total = o;
+    return lp;
+}
+
+#pragma GCC visibility push(default)
+extern "C" {
+
+size_t spkmc_state_bytes(const spkmc_params *p) {
+    std::string why;
+    if (!validate(p, why)) {
+        g_last_error = why;
+        return 0;
+    }
+    return plan(p).total;
+}
+
+spkmc_status spkmc_rate_table(const spkmc_params *p, double out[14]) {
+    std::string why;
+    if (!out) return fail(nullptr, SPKMC_E_INVAL, "out is NULL");
+    if (!validate(p, why)) return fail(nullptr, SPKMC_E_INVAL, why);
+    make_rates(p, out);
+    return SPKMC_OK;
+}
+
+spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, void *hip_stream, spkmc_ctx **out) {
+    if (!out) return fail(nullptr, SPKMC_E_INVAL, "out is NULL");
+    *out = nullptr;
+    spkmc_ctx *c = new (std::nothrow) spkmc_ctx();
+    if (!c) return fail(nullptr, SPKMC_E_NOMEM, "cannot allocate context");
+    *out = c;
+    c->failed = false;
+    c->cycle = 0;
+    std::string why;
+    if (!validate(p, why)) return fail(c, SPKMC_E_INVAL, why);
+    c->p = *p;
+    LayoutPlan lp = plan(p);
+    if (!dev_buf) return fail(c, SPKMC_E_INVAL, "dev_buf is NULL");
+    if (((uintptr_t)dev_buf) & 255) return fail(c, SPKMC_E_INVAL, "dev_buf must be 256-byte aligned");
+    if (dev_bytes < lp.total) {
+        char m[160];
+        snprintf(m, sizeof m, "dev_bytes %zu < required %zu", dev_bytes, lp.total);
+        return fail(c, SPKMC_E_RANGE, m);
+    }
+    c->stream = (hipStream_t)hip_stream;
+    c->dev = (char *)dev_buf;
+    c->dev_bytes = dev_bytes;
+    Geom &g = c->g;
+    memset(&g, 0, sizeof g);
+    g.L = p->L;
+    g.d = p->domain;
+    g.h = p->domain / 2;
+    g.nd = p->L / p->domain;
+    g.layout = p->layout;
+    g.K = (uint32_t)((uint64_t)g.nd * g.nd * g.nd);
+    g.N = (uint64_t)p->L * p->L * p->L;
+    g.h2 = (uint32_t)(g.h * g.h);
+    g.h3 = g.h2 * (uint32_t)g.h;
+    g.wpo = g.h3 / 32;
+    g.fwpo = 6 * g.h2 / 32;
+    g.rec_cap = p->record_cap;
+    g.seed = p->seed;
+    g.st = (DevState *)c->dev;
+    g.rec = (spkmc_record *)(c->dev + lp.off_rec);
+    g.Rk = (double *)(c->dev + lp.off_Rk);
+    g.hist = (uint32_t *)(c->dev + lp.off_hist);
+    g.flip = (uint64_t *)(c->dev + lp.off_flip);
+    if (p->layout == SPKMC_LAYOUT_INT8) {
+        g.spin8 = (int8_t *)(c->dev + lp.off_spin);
+    } else {
+        g.A = (uint32_t *)(c->dev + lp.off_spin);
+        g.F = (uint32_t *)(c->dev + lp.off_F);
+    }
+    make_rates(p, g.r);
+    c->spin_off = lp.off_spin;
+    c->spin_bytes = lp.spin_bytes;
+    c->rec_off = lp.off_rec;
+
+    // engine choice
+    std::string pwhy;
+    bool pers = persistent_supported(g, *p, pwhy);
+    if (p->engine == SPKMC_ENGINE_PERSISTENT && !pers) return fail(c, SPKMC_E_UNSUPPORTED, "persistent engine: " + pwhy);
+    c->engine = (p->engine == SPKMC_ENGINE_CYCLE || !pers) ? SPKMC_ENGINE_CYCLE : SPKMC_ENGINE_PERSISTENT;
+    c->grid = (int)g.K;
+    c->block = 256;
+    c->wg_domains = 0;
+    if (c->engine == SPKMC_ENGINE_PERSISTENT) {
+        hipError_t e = persistent_configure(g, *p, c->grid, c->block, c->wg_domains);
+        if (e != hipSuccess) return hip_fail(c, e, "persistent_configure");
+    }
+
+    hipError_t e;
+    if ((e = hipMemsetAsync(c->dev, 0, lp.off_spin, c->stream)) != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
+    if ((e = hipMemcpyAsync(c->dev + lp.off_rates, g.r, sizeof g.r, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "hipMemcpyAsync(rates)");
+    if ((e = launch_init(g, p->init, c->stream)) != hipSuccess) return hip_fail(c, e, "init kernel");
+    if ((e = launch_faces(g, c->stream)) != hipSuccess) return hip_fail(c, e, "face kernel");
+    if ((e = launch_observables(g, c->stream)) != hipSuccess) return hip_fail(c, e, "observables kernel");
+    return SPKMC_OK;
+}
+
+spkmc_status spkmc_run(spkmc_ctx *c, uint64_t ncycles, uint32_t obs_every) {
+    if (!c) return fail(nullptr, SPKMC_E_INVAL, "ctx is NULL");
+    if (c->failed || !c->dev) return fail(c, SPKMC_E_STATE, "context is in a failed state");
+    if (ncycles == 0) return SPKMC_OK;
+    hipError_t e = hipSuccess;
+    if (c->engine == SPKMC_ENGINE_PERSISTENT) {
+        e = launch_persistent(c->g, c->cycle, ncycles, obs_every, c->grid, c->block, c->wg_domains, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "persistent kernel launch");
+        c->cycle += ncycles;
+    } else {
+        for (uint64_t i = 0; i < ncycles; ++i) {
+            e = launch_cycle(c->g, c->cycle, obs_every, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "cycle kernel launch");
+            c->cycle += 1;
+        }
+    }
+    return SPKMC_OK;
+}
+
+static spkmc_status read_state(spkmc_ctx *c, DevState &st) {
+    hipError_t e = hipMemcpyAsync(&st, c->dev, sizeof st, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reading device state");
+    if (st.error) {
+        char m[128];
+        snprintf(m, sizeof m, "device-side wait gave up (code %u)", st.error);
+        return fail(c, SPKMC_E_DEVICE, m);
+    }
+    return SPKMC_OK;
+}
+
+spkmc_status spkmc_observables(spkmc_ctx *c, spkmc_obs *out) {
+    if (!c) return fail(nullptr, SPKMC_E_INVAL, "ctx is NULL");
+    if (!out) return fail(c, SPKMC_E_INVAL, "out is NULL");
+    if (c->failed) return fail(c, SPKMC_E_STATE, "context is in a failed state");
+    DevState st;
+    spkmc_status s = read_state(c, st);
+    if (s != SPKMC_OK) return s;
+    out->rec.cycle = st.cycle;
+    out->rec.fired = st.fired;
+    out->rec.nulls = st.nulls;
+    out->rec.t = st.t;
+    out->rec.M = st.M;
+    out->rec.B = st.B;
+    out->E = -c->p.J * (double)st.B - c->p.H * (double)st.M;
+    out->m = (double)st.M / (double)c->g.N;
+    uint64_t tot = st.fired + st.nulls;
+    out->ur = tot ? (double)st.fired / (double)tot : 0.0;
+    return SPKMC_OK;
+}
+
+spkmc_status spkmc_records(spkmc_ctx *c, spkmc_record *host, size_t cap, size_t *n) {
+    if (!c) return fail(nullptr, SPKMC_E_INVAL, "ctx is NULL");
+    if (!n || (!host && cap)) return fail(c, SPKMC_E_INVAL, "bad output arguments");
+    if (c->failed) return fail(c, SPKMC_E_STATE, "context is in a failed state");
+    DevState st;
+    spkmc_status s = read_state(c, st);
+    if (s != SPKMC_OK) return s;
+    uint64_t have = st.rec_count < c->p.record_cap ? st.rec_count : c->p.record_cap;
+    uint64_t take = have < cap ? have : cap;
+    std::vector<spkmc_record> ring(c->p.record_cap ? c->p.record_cap : 1);
+    if (c->p.record_cap) {
+        hipError_t e = hipMemcpy(ring.data(), c->dev + c->rec_off, sizeof(spkmc_record) * c->p.record_cap, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(c, e, "copying records");
+    }
+    for (uint64_t i = 0; i < take; ++i) {
+        uint64_t idx = st.rec_count - take + i;
+        host[i] = ring[idx % c->p.record_cap];
+    }
+    *n = (size_t)take;
+    return SPKMC_OK;
+}
+
+// host-side bit address of site (x, y, z) in the packed layout
+static inline uint64_t packed_bit(const Geom &g, int x, int y, int z) {
+    int kx = x / g.d, ky = y / g.d, kz = z / g.d;
+    int rx = x - kx * g.d, ry = y - ky * g.d, rz = z - kz * g.d;
+    int sx = rx >= g.h, sy = ry >= g.h, sz = rz >= g.h;
+    uint64_t k = (uint64_t)kx + (uint64_t)g.nd * ((uint64_t)ky + (uint64_t)g.nd * (uint64_t)kz);
+    uint64_t q = (uint64_t)(rx - sx * g.h) + (uint64_t)g.h * ((uint64_t)(ry - sy * g.h) + (uint64_t)g.h * (uint64_t)(rz - sz * g.h));
+    return (k * 8 + (uint64_t)(sx | (sy << 1) | (sz << 2))) * g.h3 + q;
+}
+
+spkmc_status spkmc_copy_spins(spkmc_ctx *c, int8_t *host, size_t n) {
+    if (!c) return fail(nullptr, SPKMC_E_INVAL, "ctx is NULL");
+    if (!host) return fail(c, SPKMC_E_INVAL, "host is NULL");
+    if (c->failed) return fail(c, SPKMC_E_STATE, "context is in a failed state");
+    if (n < c->g.N) return fail(c, SPKMC_E_RANGE, "host buffer smaller than N");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    const Geom &g = c->g;
+    if (g.layout == SPKMC_LAYOUT_INT8) {
+        e = hipMemcpy(host, c->dev + c->spin_off, g.N, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(c, e, "copying spins");
+        return SPKMC_OK;
+    }
+    std::vector<uint32_t> A;
+    try {
+        A.resize(g.N / 32);
+    } catch (...) {
+        return fail(c, SPKMC_E_NOMEM, "host buffer for packed spins");
+    }
+    e = hipMemcpy(A.data(), c->dev + c->spin_off, g.N / 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "copying spins");
+    // octant-major -> linear
+    for (uint64_t o = 0; o < (uint64_t)g.K * 8; ++o) {
+        uint32_t k = (uint32_t)(o >> 3);
+        int s = (int)(o & 7);
+        int kx = (int)(k % (uint32_t)g.nd), ky = (int)((k / (uint32_t)g.nd) % (uint32_t)g.nd), kz = (int)(k / ((uint32_t)g.nd * (uint32_t)g.nd));
+        int ox = kx * g.d + (s & 1) * g.h, oy = ky * g.d + ((s >> 1) & 1) * g.h, oz = kz * g.d + ((s >> 2) & 1) * g.h;
+        const uint32_t *w = &A[o * g.wpo];
+        uint32_t q = 0;
+        for (int lz = 0; lz < g.h; ++lz)
+            for (int ly = 0; ly < g.h; ++ly) {
+                int8_t *row = host + (uint64_t)ox + (uint64_t)g.L * ((uint64_t)(oy + ly) + (uint64_t)g.L * (uint64_t)(oz + lz));
+                for (int lx = 0; lx < g.h; ++lx, ++q) row[lx] = ((w[q >> 5] >> (q & 31)) & 1u) ? 1 : -1;
+            }
+    }
+    return SPKMC_OK;
+}
+
+static void host_observables(const int8_t *s, int L, int64_t &M, int64_t &B) {
+    M = 0;
+    B = 0;
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                int v = s[(int64_t)x + (int64_t)L * ((int64_t)y + (int64_t)L * z)];
+                M += v;
+                B += v * (s[(int64_t)(x + 1 == L ? 0 : x + 1) + (int64_t)L * ((int64_t)y + (int64_t)L * z)] +
+                          s[(int64_t)x + (int64_t)L * ((int64_t)(y + 1 == L ? 0 : y + 1) + (int64_t)L * z)] +
+                          s[(int64_t)x + (int64_t)L * ((int64_t)y + (int64_t)L * (z + 1 == L ? 0 : z + 1))]);
+            }
+}
+
+spkmc_status spkmc_set_spins(spkmc_ctx *c, const int8_t *host, size_t n) {
+    if (!c) return fail(nullptr, SPKMC_E_INVAL, "ctx is NULL");
+    if (!host) return fail(c, SPKMC_E_INVAL, "host is NULL");
+    if (c->failed) return fail(c, SPKMC_E_STATE, "context is in a failed state");
+    const Geom &g = c->g;
+    if (n < g.N) return fail(c, SPKMC_E_RANGE, "host buffer smaller than N");
+    for (uint64_t i = 0; i < g.N; ++i)
+        if (host[i] != 1 && host[i] != -1) return fail(c, SPKMC_E_INVAL, "spins must be +1 or -1");
+    int64_t M, B;
+    host_observables(host, g.L, M, B);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    if (g.layout == SPKMC_LAYOUT_INT8) {
+        e = hipMemcpy(c->dev + c->spin_off, host, g.N, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(c, e, "copying spins");
+    } else {
+        std::vector<uint32_t> A(g.N / 32, 0u);
+        for (int z = 0; z < g.L; ++z)
+            for (int y = 0; y < g.L; ++y)
+                for (int x = 0; x < g.L; ++x)
+                    if (host[(int64_t)x + (int64_t)g.L * ((int64_t)y + (int64_t)g.L * z)] > 0) {
+                        uint64_t b = packed_bit(g, x, y, z);
+                        A[b >> 5] |= 1u << (b & 31);
+                    }
+        e = hipMemcpy(c->dev + c->spin_off, A.data(), g.N / 8, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(c, e, "copying spins");
+        if ((e = launch_faces(g, c->stream)) != hipSuccess) return hip_fail(c, e, "face kernel");
+    }
+    DevState st;
+    e = hipMemcpy(&st, c->dev, sizeof st, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "reading state");
+    st.M = M;
+    st.B = B;
+    e = hipMemcpy(c->dev, &st, sizeof st, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "writing state");
+    return SPKMC_OK;
+}
+
+static const uint64_t kMagic = 0x31434d4b50535053ull;  // "SPSPKMC1"
+
+spkmc_status spkmc_save(spkmc_ctx *c, void *host, size_t cap, size_t *n) {
+    if (!c) return fail(nullptr, SPKMC_E_INVAL, "ctx is NULL");
+    if (!n) return fail(c, SPKMC_E_INVAL, "n is NULL");
+    if (c->failed) return fail(c, SPKMC_E_STATE, "context is in a failed state");
+    size_t need = 8 + sizeof(spkmc_params) + 8 + c->spin_off + c->spin_bytes;
+    *n = need;
+    if (!host) return SPKMC_OK;
+    if (cap < need) return fail(c, SPKMC_E_RANGE, "checkpoint buffer too small");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    char *o = (char *)host;
+    memcpy(o, &kMagic, 8);
+    memcpy(o + 8, &c->p, sizeof(spkmc_params));
+    memcpy(o + 8 + sizeof(spkmc_params), &c->cycle, 8);
+    // DevState, rates, records, per-domain scratch and spins, as laid out on the device
+    e = hipMemcpy(o + 16 + sizeof(spkmc_params), c->dev, c->spin_off + c->spin_bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "copying state");
+    return SPKMC_OK;
+}
+
+spkmc_status spkmc_load(spkmc_ctx *c, const void *host, size_t n) {
+    if (!c) return fail(nullptr, SPKMC_E_INVAL, "ctx is NULL");
+    if (!host) return fail(c, SPKMC_E_INVAL, "host is NULL");
+    if (c->failed) return fail(c, SPKMC_E_STATE, "context is in a failed state");
+    size_t need = 8 + sizeof(spkmc_params) + 8 + c->spin_off + c->spin_bytes;
+    if (n != need) return fail(c, SPKMC_E_INVAL, "checkpoint size does not match these parameters");
+    const char *o = (const char *)host;
+    uint64_t magic;
+    memcpy(&magic, o, 8);
+    if (magic != kMagic) return fail(c, SPKMC_E_INVAL, "not a checkpoint");
+    spkmc_params p;
+    memcpy(&p, o + 8, sizeof p);
+    // the initial-state choice and the launch shape do not change the meaning of a saved state
+    p.init = c->p.init;
+    p.engine = c->p.engine;
+    p.wg_domains = c->p.wg_domains;
+    if (memcmp(&p, &c->p, sizeof p) != 0) return fail(c, SPKMC_E_INVAL, "checkpoint parameters differ");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    e = hipMemcpy(c->dev, o + 16 + sizeof(spkmc_params), c->spin_off + c->spin_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "copying state");
+    memcpy(&c->cycle, o + 8 + sizeof(spkmc_params), 8);
+    return SPKMC_OK;
+}
+
+spkmc_status spkmc_query(const spkmc_ctx *c, spkmc_info *out) {
+    if (!c || !out) return fail(nullptr, SPKMC_E_INVAL, "NULL argument");
+    out->engine = c->engine;
+    out->layout = c->g.layout;
+    out->h = c->g.h;
+    out->grid = c->grid;
+    out->block = c->block;
+    out->wg_domains = c->wg_domains;
+    out->K = c->g.K;
+    out->N = c->g.N;
+    out->state_bytes = c->spin_off + c->spin_bytes;
+    double h = c->g.h;
+    out->bytes_per_cycle = (double)c->g.K * ((h * h * h + 6.0 * h * h) / 8.0 + 8.0);
+    return SPKMC_OK;
+}
+
+const char *spkmc_last_error(const spkmc_ctx *c) {
+    if (c) return c->err.empty() ? "no error" : c->err.c_str();
+    return g_last_error.c_str();
+}
+
+void spkmc_destroy(spkmc_ctx *c) { delete c; }
+
+}  // extern "C"
+#pragma GCC visibility pop

@@ -1,0 +1,207 @@
+"""Thin Python binding of the C ABI in include/spkmc.h (argument marshalling only).
+
+Every step of the spkMC cycle runs in the HIP kernels of ``libspkmc.so``;
+PyTorch only provides the device buffer and the stream.  Importing this module
+fails loudly if the library has not been built (there is no CPU fallback).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspkmc.so")
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_RANGE, E_UNSUPPORTED = range(7)
+RATES = {"glauber": 0, "metropolis": 1}
+INITS = {"random": 0, "up": 1, "down": 2}
+LAYOUTS = {"int8": 0, "packed": 1}
+ENGINES = {"auto": 0, "cycle": 1, "persistent": 2}
+
+
+class Params(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("L", C.c_int32), ("domain", C.c_int32), ("rates", C.c_int32),
+                ("J", C.c_double), ("H", C.c_double), ("T", C.c_double), ("seed", C.c_uint64),
+                ("init", C.c_int32), ("layout", C.c_int32), ("engine", C.c_int32), ("wg_domains", C.c_int32),
+                ("record_cap", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class Record(C.Structure):
+    _fields_ = [("cycle", C.c_uint64), ("fired", C.c_uint64), ("nulls", C.c_uint64), ("t", C.c_double),
+                ("M", C.c_int64), ("B", C.c_int64)]
+
+    def as_tuple(self):
+        return (self.cycle, self.fired, self.nulls, self.t, self.M, self.B)
+
+
+class Obs(C.Structure):
+    _fields_ = [("rec", Record), ("E", C.c_double), ("m", C.c_double), ("ur", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("engine", C.c_int32), ("layout", C.c_int32), ("h", C.c_int32), ("grid", C.c_int32),
+                ("block", C.c_int32), ("wg_domains", C.c_int32), ("K", C.c_uint64), ("N", C.c_uint64),
+                ("state_bytes", C.c_uint64), ("bytes_per_cycle", C.c_double)]
+
+
+EXPORTS = ["spkmc_state_bytes", "spkmc_init", "spkmc_run", "spkmc_observables", "spkmc_records",
+           "spkmc_copy_spins", "spkmc_set_spins", "spkmc_rate_table", "spkmc_save", "spkmc_load",
+           "spkmc_query", "spkmc_last_error", "spkmc_destroy"]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1005_4713_amd.build` "
+                          "(there is no fallback path)")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    P = C.POINTER
+    lib.spkmc_state_bytes.restype = C.c_size_t
+    lib.spkmc_state_bytes.argtypes = [P(Params)]
+    lib.spkmc_init.restype = C.c_int
+    lib.spkmc_init.argtypes = [P(Params), vp, C.c_size_t, vp, P(vp)]
+    lib.spkmc_run.restype = C.c_int
+    lib.spkmc_run.argtypes = [vp, C.c_uint64, C.c_uint32]
+    lib.spkmc_observables.restype = C.c_int
+    lib.spkmc_observables.argtypes = [vp, P(Obs)]
+    lib.spkmc_records.restype = C.c_int
+    lib.spkmc_records.argtypes = [vp, P(Record), C.c_size_t, P(C.c_size_t)]
+    lib.spkmc_copy_spins.restype = C.c_int
+    lib.spkmc_copy_spins.argtypes = [vp, P(C.c_int8), C.c_size_t]
+    lib.spkmc_set_spins.restype = C.c_int
+    lib.spkmc_set_spins.argtypes = [vp, P(C.c_int8), C.c_size_t]
+    lib.spkmc_rate_table.restype = C.c_int
+    lib.spkmc_rate_table.argtypes = [P(Params), P(C.c_double)]
+    lib.spkmc_save.restype = C.c_int
+    lib.spkmc_save.argtypes = [vp, vp, C.c_size_t, P(C.c_size_t)]
+    lib.spkmc_load.restype = C.c_int
+    lib.spkmc_load.argtypes = [vp, vp, C.c_size_t]
+    lib.spkmc_query.restype = C.c_int
+    lib.spkmc_query.argtypes = [vp, P(Info)]
+    lib.spkmc_last_error.restype = C.c_char_p
+    lib.spkmc_last_error.argtypes = [vp]
+    lib.spkmc_destroy.restype = None
+    lib.spkmc_destroy.argtypes = [vp]
+    return lib
+
+
+lib = _load()
+
+
+class SpkmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"spkmc status {status}: {msg}")
+        self.status = status
+
+
+def make_params(L, domain, J=1.0, H=0.0, T=4.5115, seed=1, rates="glauber", init="random",
+                layout="packed", engine="auto", wg_domains=0, record_cap=1024):
+    p = Params()
+    p.struct_size = C.sizeof(Params)
+    p.L, p.domain = int(L), int(domain)
+    p.rates = RATES[rates] if isinstance(rates, str) else int(rates)
+    p.J, p.H, p.T = float(J), float(H), float(T)
+    p.seed = int(seed)
+    p.init = INITS[init] if isinstance(init, str) else int(init)
+    p.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+    p.engine = ENGINES[engine] if isinstance(engine, str) else int(engine)
+    p.wg_domains = int(wg_domains)
+    p.record_cap = int(record_cap)
+    p.reserved = 0
+    return p
+
+
+def state_bytes(params):
+    return lib.spkmc_state_bytes(C.byref(params))
+
+
+def rate_table(params):
+    out = (C.c_double * 14)()
+    st = lib.spkmc_rate_table(C.byref(params), out)
+    if st != OK:
+        raise SpkmcError(st, lib.spkmc_last_error(None).decode())
+    return np.array(list(out))
+
+
+class Sim:
+    """One lattice on one GPU: the device buffer is a torch uint8 tensor, the
+    work runs on torch's current stream of ``device``."""
+
+    def __init__(self, L, domain, device=None, **kw):
+        import torch
+        self.params = make_params(L, domain, **kw)
+        nbytes = state_bytes(self.params)
+        if nbytes == 0:
+            raise SpkmcError(E_INVAL, lib.spkmc_last_error(None).decode())
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        # 256-byte alignment: the caching allocator returns 512-byte aligned blocks
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.spkmc_init(C.byref(self.params), C.c_void_p(self.buf.data_ptr()), nbytes,
+                                C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx))
+        if st != OK:
+            msg = lib.spkmc_last_error(self.ctx if self.ctx else None).decode()
+            self._free()
+            raise SpkmcError(st, msg)
+        self.L = int(L)
+        self.N = self.L ** 3
+
+    def _free(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            lib.spkmc_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        self._free()
+
+    def _check(self, st):
+        if st != OK:
+            raise SpkmcError(st, lib.spkmc_last_error(self.ctx).decode())
+
+    def run(self, ncycles, obs_every=0):
+        self._check(lib.spkmc_run(self.ctx, int(ncycles), int(obs_every)))
+
+    def observables(self):
+        o = Obs()
+        self._check(lib.spkmc_observables(self.ctx, C.byref(o)))
+        return {"cycle": o.rec.cycle, "fired": o.rec.fired, "nulls": o.rec.nulls, "t": o.rec.t,
+                "M": o.rec.M, "B": o.rec.B, "E": o.E, "m": o.m, "ur": o.ur}
+
+    def state(self):
+        o = Obs()
+        self._check(lib.spkmc_observables(self.ctx, C.byref(o)))
+        return o.rec.as_tuple()
+
+    def records(self, cap=None):
+        cap = self.params.record_cap if cap is None else cap
+        buf = (Record * max(cap, 1))()
+        n = C.c_size_t()
+        self._check(lib.spkmc_records(self.ctx, buf, cap, C.byref(n)))
+        return [buf[i].as_tuple() for i in range(n.value)]
+
+    def spins(self):
+        out = np.empty(self.N, dtype=np.int8)
+        self._check(lib.spkmc_copy_spins(self.ctx, out.ctypes.data_as(C.POINTER(C.c_int8)), out.size))
+        return out
+
+    def set_spins(self, spins):
+        spins = np.ascontiguousarray(spins, dtype=np.int8)
+        self._check(lib.spkmc_set_spins(self.ctx, spins.ctypes.data_as(C.POINTER(C.c_int8)), spins.size))
+
+    def save(self):
+        n = C.c_size_t()
+        self._check(lib.spkmc_save(self.ctx, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(lib.spkmc_save(self.ctx, buf, n.value, C.byref(n)))
+        return buf.raw
+
+    def load(self, blob):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._check(lib.spkmc_load(self.ctx, buf, len(blob)))
+
+    def info(self):
+        i = Info()
+        self._check(lib.spkmc_query(self.ctx, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in Info._fields_}

@@ -1,0 +1,100 @@
+"""The C ABI without a GPU: the library loads, exports every entry point that
+include/spkmc.h declares, validates parameters and computes the same FP64 rate
+table as the oracle bit for bit."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1005_4713_amd", "libspkmc.so")
+
+
+@pytest.fixture(scope="module")
+def spkmc():
+    if not os.path.exists(LIB):
+        from paper_1005_4713_amd import build
+        build.build()
+    from paper_1005_4713_amd import spkmc as mod
+    return mod
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "spkmc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(spkmc_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(spkmc):
+    names = _declared()
+    assert len(names) >= 13
+    lib = C.CDLL(LIB)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(spkmc.EXPORTS) == names
+
+
+def test_struct_sizes_match_header(spkmc):
+    # field layout of the ctypes mirrors: 72-byte params, 48-byte record
+    assert C.sizeof(spkmc.Params) == 72
+    assert C.sizeof(spkmc.Record) == 48
+    assert C.sizeof(spkmc.Obs) == 72
+
+
+@pytest.mark.parametrize("kw", [dict(L=16, domain=3), dict(L=16, domain=6), dict(L=1, domain=2),
+                                dict(L=16, domain=8, T=0.0), dict(L=16, domain=8, T=-1.0),
+                                dict(L=16, domain=8, T=1e-3), dict(L=12, domain=6, layout="packed"),
+                                dict(L=16, domain=4, layout="packed"), dict(L=16, domain=8, rates=7),
+                                dict(L=16, domain=8, init=5), dict(L=16, domain=8, engine=9)])
+def test_invalid_parameters(spkmc, kw):
+    p = spkmc.make_params(**kw)
+    assert spkmc.state_bytes(p) == 0
+    assert spkmc.lib.spkmc_last_error(None)
+    with pytest.raises(spkmc.SpkmcError):
+        spkmc.rate_table(p)
+    ctx = C.c_void_p()
+    st = spkmc.lib.spkmc_init(C.byref(p), None, 0, None, C.byref(ctx))
+    assert st == spkmc.E_INVAL
+    spkmc.lib.spkmc_destroy(ctx)
+
+
+def test_struct_size_checked(spkmc):
+    p = spkmc.make_params(16, 8)
+    p.struct_size = 64
+    assert spkmc.state_bytes(p) == 0
+    p = spkmc.make_params(16, 8)
+    p.reserved = 1
+    assert spkmc.state_bytes(p) == 0
+
+
+def test_buffer_too_small_rejected(spkmc):
+    p = spkmc.make_params(16, 8, layout="int8")
+    need = spkmc.state_bytes(p)
+    assert need > 16 ** 3
+    ctx = C.c_void_p()
+    st = spkmc.lib.spkmc_init(C.byref(p), C.c_void_p(1 << 20), need - 1, None, C.byref(ctx))
+    assert st == spkmc.E_RANGE
+    spkmc.lib.spkmc_destroy(ctx)
+
+
+@pytest.mark.parametrize("rates", ["glauber", "metropolis"])
+@pytest.mark.parametrize("J,H,T", [(1.0, 0.0, 4.5115), (1.0, 0.05, 4.4), (1.0, -0.05, 4.6), (0.0, 0.3, 1.0),
+                                   (-0.5, 0.1, 2.0), (1.0, 0.0, 1e3)])
+def test_rate_table_bitwise_equals_oracle(spkmc, rates, J, H, T):
+    p = spkmc.make_params(16, 8, J=J, H=H, T=T, rates=rates)
+    lib_tab = spkmc.rate_table(p)
+    orc_tab = oracle.rate_table(J, H, T, 0 if rates == "glauber" else 1)
+    assert np.array_equal(lib_tab.view(np.uint64), orc_tab.view(np.uint64))
+
+
+def test_state_bytes_scale(spkmc):
+    # packed 1024^3 with d = 32: bits of the spins, their face copies and per-domain scratch
+    p = spkmc.make_params(1024, 32, layout="packed")
+    nb = spkmc.state_bytes(p)
+    K = 32 ** 3
+    assert nb >= 1024 ** 3 // 8 + K * 8 * 6 * 16 * 16 // 8
+    assert nb < 1024 ** 3 // 8 * 1.5
