@@ -76,7 +76,7 @@ static int make_rates(const spkmc_params *p, double out[14]) {
 }
 
 struct LayoutPlan {
-    size_t off_rates, off_rec, off_Rk, off_hist, off_flip, off_spin, off_F, total, spin_bytes;
+    size_t off_rates, off_rec, off_Rk, off_hist, off_flip, off_sync, off_spin, off_F, total, spin_bytes;
 };
 
 static bool validate(const spkmc_params *p, std::string &why) {
@@ -111,6 +111,8 @@ static LayoutPlan plan(const spkmc_params *p) {
     lp.off_Rk = o; o = align256(o + K * 8);
     lp.off_hist = o; o = align256(o + K * 64);
     lp.off_flip = o; o = align256(o + K * 8);
+    // persistent engine: at most K / 16 + 1 workgroups (16 domains or more each), 9 words each
+    lp.off_sync = o; o = align256(o + (9 * (K / 16 + 2) + 16) * 8);
     lp.off_spin = o;
     if (p->layout == SPKMC_LAYOUT_INT8) {
         o = align256(o + N);
@@ -187,6 +189,7 @@ spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, 
     g.Rk = (double *)(c->dev + lp.off_Rk);
     g.hist = (uint32_t *)(c->dev + lp.off_hist);
     g.flip = (uint64_t *)(c->dev + lp.off_flip);
+    g.sync = (uint64_t *)(c->dev + lp.off_sync);
     if (p->layout == SPKMC_LAYOUT_INT8) {
         g.spin8 = (int8_t *)(c->dev + lp.off_spin);
     } else {

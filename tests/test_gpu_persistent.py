@@ -1,0 +1,134 @@
+"""GPU parity of the persistent engine (one cooperative launch per spkmc_run):
+against the CPU oracle, against the per-cycle engine, and across launch shapes.
+Bar: spins, fired/null counts, M and B bit-exact; clock within 1e-12 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+T_REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def spkmc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1005_4713_amd import spkmc as mod
+    return mod
+
+
+def _same(g, o):
+    assert g[0] == o[0] and g[1] == o[1] and g[2] == o[2], (g, o)
+    assert g[4] == o[4] and g[5] == o[5], (g, o)
+    assert abs(g[3] - o[3]) <= T_REL * abs(o[3]), (g, o)
+
+
+def _orc(L, d, **kw):
+    kw = dict(kw)
+    kw["rates"] = {"glauber": 0, "metropolis": 1}[kw.get("rates", "glauber")]
+    kw["init"] = {"random": 0, "up": 1, "down": 2}[kw.get("init", "random")]
+    return oracle.Sim(L=L, d=d, **kw)
+
+
+@pytest.mark.parametrize("L,d,kw", [
+    (64, 32, dict()),                                        # h = 16, one workgroup
+    (128, 32, dict(rates="metropolis", H=0.05)),             # h = 16, two workgroups
+    (256, 32, dict(init="up", T=4.4)),                       # h = 16, sixteen workgroups
+    (32, 16, dict()),                                        # h = 8, 8 domains
+    (64, 16, dict(H=-0.05, T=4.6)),                          # h = 8, one full workgroup
+    (128, 16, dict(rates="metropolis", init="down")),        # h = 8, eight workgroups
+])
+def test_persistent_vs_oracle(spkmc, L, d, kw):
+    print("case", L, d, kw, flush=True)
+    kw.setdefault("T", 4.5115)
+    gpu = spkmc.Sim(L, d, layout="packed", engine="persistent", seed=5, record_cap=256, **kw)
+    info = gpu.info()
+    assert info["engine"] == spkmc.ENGINES["persistent"]
+    orc = _orc(L, d, seed=5, **kw)
+    # launches of different lengths, records every 10 cycles across launch boundaries
+    n_done = 0
+    for n in (37, 63, 100):
+        gpu.run(n, obs_every=10)
+        ro = orc.run(n, obs_every=10)
+        n_done += n
+        rg = gpu.records(len(ro)) if ro else []
+        assert len(rg) == len(ro)
+        for g_, o_ in zip(rg, ro):
+            _same(g_, o_)
+        _same(gpu.state(), orc.state())
+        assert np.array_equal(gpu.spins(), orc.spins())
+
+
+@pytest.mark.parametrize("L,d", [(256, 32), (256, 16)])
+def test_persistent_equals_cycle_engine(spkmc, L, d):
+    print("case", L, d, flush=True)
+    a = spkmc.Sim(L, d, layout="packed", engine="persistent", seed=9, record_cap=64)
+    b = spkmc.Sim(L, d, layout="packed", engine="cycle", seed=9, record_cap=64)
+    a.run(300, obs_every=25)
+    b.run(300, obs_every=25)
+    assert a.records() == b.records()
+    assert a.state() == b.state()
+    assert np.array_equal(a.spins(), b.spins())
+
+
+def test_launch_shapes_bit_identical(spkmc):
+    """Different domains per workgroup (and so different workgroup counts and
+    neighbour sets) must give the same trajectory bit for bit."""
+    outs = []
+    for L, d, shapes in ((256, 32, (32, 64, 128)), (256, 16, (64, 128, 256))):
+        ref = None
+        for wd in shapes:
+            print("case", L, d, wd, flush=True)
+            s = spkmc.Sim(L, d, layout="packed", engine="persistent", wg_domains=wd, seed=13, record_cap=64)
+            assert s.info()["wg_domains"] == wd
+            s.run(120, obs_every=1)
+            out = (s.records(), s.state(), s.spins().tobytes())
+            if ref is None:
+                ref = out
+            else:
+                assert out == ref, (L, d, wd)
+        outs.append(ref)
+
+
+def test_single_cycle_launches(spkmc):
+    a = spkmc.Sim(128, 32, layout="packed", engine="persistent", seed=3, record_cap=64)
+    b = spkmc.Sim(128, 32, layout="packed", engine="persistent", seed=3, record_cap=64)
+    for _ in range(30):
+        a.run(1, obs_every=3)
+    b.run(30, obs_every=3)
+    assert a.records() == b.records()
+    assert a.state() == b.state()
+    assert np.array_equal(a.spins(), b.spins())
+
+
+def test_large_l512_first_cycles(spkmc):
+    """L = 512 (2^27 sites), d = 16: the first cycles against the oracle."""
+    print("case L512 d16", flush=True)
+    gpu = spkmc.Sim(512, 16, layout="packed", engine="auto", T=4.5115, seed=3, record_cap=16)
+    orc = _orc(512, 16, T=4.5115, seed=3)
+    for n in (2, 3):
+        gpu.run(n, obs_every=1)
+        ro = orc.run(n, obs_every=1)
+        for g_, o_ in zip(gpu.records(n), ro):
+            _same(g_, o_)
+    assert np.array_equal(gpu.spins(), orc.spins())
+
+
+def test_headline_l1024_first_cycles(spkmc):
+    """L = 1024 (2^30 sites), d = 32, T = 4.5115, seed 42, in the launch shape the
+    benchmark uses: two cycles against the oracle, every spin compared."""
+    print("case L1024 d32", flush=True)
+    from paper_1005_4713_amd import workloads
+    w = workloads.HEADLINE_L1024
+    gpu = spkmc.Sim(w["L"], w["domain"], layout="packed", engine="auto", T=w["T"], seed=w["seed"], record_cap=16)
+    assert gpu.info()["engine"] == spkmc.ENGINES["persistent"]
+    orc = _orc(w["L"], w["domain"], T=w["T"], seed=w["seed"])
+    _same(gpu.state(), orc.state())
+    gpu.run(2, obs_every=1)
+    ro = orc.run(2, obs_every=1)
+    for g_, o_ in zip(gpu.records(2), ro):
+        _same(g_, o_)
+    assert np.array_equal(gpu.spins(), orc.spins())
