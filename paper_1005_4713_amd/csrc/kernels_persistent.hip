@@ -5,32 +5,37 @@
 // Work decomposition
 //   * A 16-lane DPP row owns one domain; a workgroup of B threads owns
 //     D = P * B / 16 consecutive domains (numbered kx + nd (ky + nd kz)) for the
-//     whole launch, processed in P passes whose per-site state stays in
-//     registers across the R_max exchange.
+//     whole launch, processed in P passes whose class planes stay in registers
+//     across the R_max exchange.
 //   * h = 16: lane l of the row holds plane lz = l of the octant (8 words, two
 //     16-site x rows each); h = 8: lane l holds word l (four 8-site rows of
 //     plane l / 2).  The z neighbours come from the adjacent lanes through DPP
 //     row shifts, the y neighbours from the word below / above, the x
 //     neighbours from in-word shifts; the 1-site halo comes from the face
-//     copies of the six neighbouring octants.
-//   * The number of up neighbours of 32 sites is counted bit-sliced (two full
-//     adders and a 2-bit add), and the 14-class histogram of the octant is
-//     recovered from 13 popcounts of products of the count bit planes and the
-//     spin plane (inclusion-exclusion; n_up = 7 never occurs).
+//     copies of the six neighbouring octants (z faces staged per row in LDS).
+//   * The up neighbours of 32 sites are counted bit-sliced (two full adders
+//     and a 2-bit add, one v_bitop3 each), and the 14-class histogram of the
+//     octant is recovered from 13 popcounts of products of the count bit planes
+//     and the spin plane (inclusion-exclusion; n_up = 7 never occurs).
 //
 // Synchronisation (no cache-flushing fences: every word another workgroup may
 // write is read with device-coherent loads, and every write is an atomic)
-//   * R_max (step 2): each workgroup stores its local maximum with the cycle
-//     parity in the sign bit (all rates are positive) into its own slot and
-//     polls all slots; the maximum is exact and order-free.
+//   * R_max (step 2): each workgroup stores its local maximum into its own slot
+//     of bank n & 1 with the generation (n >> 1) & 1 in the sign bit (all rates
+//     are positive) and polls all slots of the bank; the maximum is exact and
+//     order-free.  Two banks keep a fast workgroup's next value from
+//     overwriting one a slow workgroup has not read yet.
 //   * boundary events (step 6): after its flips a workgroup publishes the
 //     cycle number in its flag.  Before binning cycle n + 1 a workgroup only
 //     waits for the neighbouring workgroups the colour change s_n -> s_n+1
 //     makes it depend on: the halo of colour s' holds flipped sites of colour
 //     s_n only if s_n = s' ^ (1 << b), and then only from the neighbour domain
-//     along axis b.
-//   * the clock (step 5) is advanced identically by every workgroup;
-//     counters are reduced at observation cycles and at the end of the launch.
+//     along axis b.  Flips of older cycles are covered by the R_max exchange
+//     (a workgroup publishes its slot for cycle n only after its flips of
+//     cycle n - 1 are complete).
+//   * the clock (step 5) is advanced identically by every workgroup; each
+//     workgroup stores its counter partials at an observation cycle, and
+//     workgroup 0 sums them two cycles later while it waits for R_max.
 // Every wait is bounded in wall-clock time; a timeout sets DevState::error and
 // every workgroup leaves the loop.
 #include <string>
@@ -41,16 +46,19 @@ namespace spkmc {
 
 namespace {
 
-constexpr int kMaxNbr = 16;           // neighbour workgroups per direction kept in LDS
-constexpr int kMaxGrid = 2048;        // workgroups of one persistent launch
+constexpr int kMaxNbr = 16;                      // neighbour workgroups per direction kept in LDS
+constexpr int kMaxGrid = 2048;                   // workgroups of one persistent launch
+constexpr int kMaxWgDomains = 256;               // domains of one workgroup
+constexpr int kRecBanks = 4;                     // record partial banks
 constexpr uint64_t kTimeoutTicks = 200000000ull;  // 2 s of the 100 MHz wall clock
 
-// Device scratch of the persistent engine (its own region of the state, 9 G words).
+// Device scratch of the persistent engine (its own region of the state).
 struct PersistScratch {
-    uint64_t *slot;     // 2 x G: R_max of each workgroup; bank n & 1, generation (n >> 1) & 1 in bit 63
-    uint64_t *flag;     // G: cycles whose flips are complete
-    int64_t *recp;      // 2 x G x 3: record partials (fired, dM, dB) since launch start
+    uint64_t *slot;  // 2 x G: R_max of each workgroup, generation bit 63
+    uint64_t *flag;  // G: cycles whose flips are complete
+    int64_t *recp;   // kRecBanks x G x 3: counter partials (fired, dM, dB) since launch start
 };
+constexpr uint64_t kScratchWordsPerWg = 2 + 1 + 3 * kRecBanks;
 
 __device__ __forceinline__ uint32_t ld32(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -64,16 +72,40 @@ __device__ __forceinline__ void st64(uint64_t *p, uint64_t v) {
 __device__ __forceinline__ uint64_t ld_words2(const uint32_t *p) {  // two consecutive words, 8-byte aligned
     return ld64(reinterpret_cast<const uint64_t *>(p));
 }
-__device__ __forceinline__ uint32_t flip_word(uint32_t *p, uint32_t m) {
-    return __hip_atomic_fetch_xor(p, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void flip_word(uint32_t *p, uint32_t m) {
+    (void)__hip_atomic_fetch_xor(p, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// v_bitop3: any boolean function of three words; the immediate is its truth
+// table with a = 0xF0, b = 0xCC, c = 0xAA.
+constexpr int kXor3 = 0x96, kMaj3 = 0xE8, kAnd3 = 0x80, kSelAC_BnC = 0xE4;  // (a & c) | (b & ~c)
+template <int TT>
+__device__ __forceinline__ uint32_t bop(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
 }
 
 template <int CTRL>
-__device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t src) {
+__device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t src) {  // lanes shifted in from outside the row keep old
     return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, CTRL, 0xF, 0xF, false);
 }
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp0(uint32_t src) {  // lanes shifted in from outside the row read 0
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)src, CTRL, 0xF, 0xF, true);
+}
 constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114,
-              kRowShr8 = 0x118;
+              kRowShr8 = 0x118, kRowBcast = 0x150;
+template <int CTRL>
+__device__ __forceinline__ uint32_t bcast(uint32_t v) {  // lane CTRL & 15 of each row to the whole row
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t bcast_lane(uint32_t v, int lane) {  // lane 0..3 of each row (folds when unrolled)
+    switch (lane) {
+        case 0: return bcast<kRowBcast + 0>(v);
+        case 1: return bcast<kRowBcast + 1>(v);
+        case 2: return bcast<kRowBcast + 2>(v);
+        default: return bcast<kRowBcast + 3>(v);
+    }
+}
 
 __device__ __forceinline__ uint32_t align_hi(uint32_t hi, uint32_t lo, uint32_t s) {
     return __builtin_amdgcn_alignbit(hi, lo, s);  // ({hi, lo} >> s)[31:0]
@@ -97,26 +129,22 @@ __device__ __forceinline__ int wrapp(int v, int nd) { return v + 1 == nd ? 0 : v
 
 // The six halo faces of octant (k, s): for each axis the face of the octant of
 // colour s ^ (1 << axis) that touches it from below (x1/y1/z1 face) and from
-// above (x0/y0/z0 face).
+// above (x0/y0/z0 face).  nb holds the six neighbour domains of k
+// (-x, +x, -y, +y, -z, +z).
 struct HaloFaces {
     const uint32_t *lo[3];  // face at local coordinate h - 1 of the octant below
     const uint32_t *hi[3];  // face at local coordinate 0 of the octant above
 };
-__device__ __forceinline__ HaloFaces halo_faces(const Geom &g, uint32_t k, int s) {
-    DomainCoord c = dcoord(k, g.nd);
-    int kc[3] = {c.kx, c.ky, c.kz};
+__device__ __forceinline__ HaloFaces halo_faces(const Geom &g, uint32_t k, int s, const uint32_t *nb) {
     HaloFaces hf;
     const uint32_t fw = g.h2 / 32;  // words per face
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        int bit = (s >> a) & 1;
-        int nb = s ^ (1 << a);
-        int km[3] = {kc[0], kc[1], kc[2]}, kp[3] = {kc[0], kc[1], kc[2]};
-        if (!bit) km[a] = wrapm(kc[a], g.nd);  // below lies in the previous domain
-        if (bit) kp[a] = wrapp(kc[a], g.nd);   // above lies in the next domain
-        uint32_t kmi = dindex(km[0], km[1], km[2], g.nd), kpi = dindex(kp[0], kp[1], kp[2], g.nd);
-        hf.lo[a] = g.F + ((uint64_t)kmi * 8 + nb) * g.fwpo + (2 * a + 1) * fw;
-        hf.hi[a] = g.F + ((uint64_t)kpi * 8 + nb) * g.fwpo + (2 * a) * fw;
+        const int bit = (s >> a) & 1;
+        const uint32_t c = (uint32_t)(s ^ (1 << a));
+        const uint32_t kmi = bit ? k : nb[2 * a], kpi = bit ? nb[2 * a + 1] : k;  // below / above
+        hf.lo[a] = g.F + ((uint64_t)kmi * 8 + c) * g.fwpo + (2 * a + 1) * fw;
+        hf.hi[a] = g.F + ((uint64_t)kpi * 8 + c) * g.fwpo + (2 * a) * fw;
     }
     return hf;
 }
@@ -126,7 +154,6 @@ __device__ __forceinline__ HaloFaces halo_faces(const Geom &g, uint32_t k, int s
 // ---------------------------------------------------------------------------
 template <int H>
 struct Planes;
-
 template <>
 struct Planes<16> {
     static constexpr int W = 8;  // words per lane
@@ -138,33 +165,33 @@ struct Planes<8> {
     uint32_t S[W], b0[W], b1[W], b2[W];
 };
 
+// bit-sliced sum of six words: (o2 o1 o0) = number of set inputs at every bit
 __device__ __forceinline__ void count6(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e, uint32_t f,
                                        uint32_t &o0, uint32_t &o1, uint32_t &o2) {
-    uint32_t s1 = a ^ b ^ c, c1 = (a & b) | (c & (a ^ b));
-    uint32_t s2 = d ^ e ^ f, c2 = (d & e) | (f & (d ^ e));
+    uint32_t s1 = bop<kXor3>(a, b, c), c1 = bop<kMaj3>(a, b, c);
+    uint32_t s2 = bop<kXor3>(d, e, f), c2 = bop<kMaj3>(d, e, f);
     o0 = s1 ^ s2;
     uint32_t k0 = s1 & s2;
-    o1 = c1 ^ c2 ^ k0;
-    o2 = (c1 & c2) | (k0 & (c1 ^ c2));
+    o1 = bop<kXor3>(c1, c2, k0);
+    o2 = bop<kMaj3>(c1, c2, k0);
 }
 
 // 13 moments: pop(S), pop(b0), pop(b1), pop(b2), pop(b0b1), pop(b0b2), pop(b1b2)
 // and the same six products with S.
 __device__ __forceinline__ void moments(uint32_t S, uint32_t b0, uint32_t b1, uint32_t b2, uint32_t (&m)[13]) {
-    uint32_t p01 = b0 & b1, p02 = b0 & b2, p12 = b1 & b2;
     m[0] += __builtin_popcount(S);
     m[1] += __builtin_popcount(b0);
     m[2] += __builtin_popcount(b1);
     m[3] += __builtin_popcount(b2);
-    m[4] += __builtin_popcount(p01);
-    m[5] += __builtin_popcount(p02);
-    m[6] += __builtin_popcount(p12);
+    m[4] += __builtin_popcount(b0 & b1);
+    m[5] += __builtin_popcount(b0 & b2);
+    m[6] += __builtin_popcount(b1 & b2);
     m[7] += __builtin_popcount(S & b0);
     m[8] += __builtin_popcount(S & b1);
     m[9] += __builtin_popcount(S & b2);
-    m[10] += __builtin_popcount(S & p01);
-    m[11] += __builtin_popcount(S & p02);
-    m[12] += __builtin_popcount(S & p12);
+    m[10] += __builtin_popcount(bop<kAnd3>(S, b0, b1));
+    m[11] += __builtin_popcount(bop<kAnd3>(S, b0, b2));
+    m[12] += __builtin_popcount(bop<kAnd3>(S, b1, b2));
 }
 
 // Histogram (class c = 7 [s = +1] + a) from the moments of an octant of n sites.
@@ -193,51 +220,64 @@ __device__ __forceinline__ void hist_from_moments(const uint32_t (&m)[13], uint3
     }
 }
 
+// Raw words of one pass, loaded ahead of the pass that uses them.
+template <int H>
+struct Raw;
+template <>
+struct Raw<16> {
+    uint32_t W[8];            // own plane: word p = rows 2p, 2p + 1
+    uint32_t xm, xp, ym, yp;  // words holding this plane's halo rows in the x and y faces
+    uint32_t zw;              // lanes 0..7: word l of the face below, lanes 8..15: word l-8 of the face above
+};
+template <>
+struct Raw<8> {
+    uint32_t w, xm, xp, yface, zface;
+};
+
 // --- h = 16 --------------------------------------------------------------------
 // lane l = plane lz; word p holds rows ly = 2p (bits 0..15) and 2p + 1 (bits 16..31).
-__device__ __forceinline__ void bin_octant16(const Geom &g, uint32_t k, int s, bool valid, int l,
-                                             Planes<16> &P, uint32_t (&m)[13]) {
-    uint32_t W[8], zf[8];
-    uint32_t xm = 0, xp = 0, ym = 0, yp = 0;
+__device__ __forceinline__ void load16(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb, Raw<16> &r) {
 #pragma unroll
-    for (int p = 0; p < 8; ++p) { W[p] = 0; zf[p] = 0; }
-    if (valid) {
-        const uint32_t *A = g.A + ((uint64_t)k * 8 + s) * 128 + l * 8;
+    for (int p = 0; p < 8; ++p) r.W[p] = 0;
+    r.xm = r.xp = r.ym = r.yp = r.zw = 0;
+    if (!valid) return;
+    const uint32_t *A = g.A + ((uint64_t)k * 8 + s) * 128 + l * 8;
 #pragma unroll
-        for (int p = 0; p < 8; p += 2) {
-            uint64_t v = ld_words2(A + p);
-            W[p] = (uint32_t)v;
-            W[p + 1] = (uint32_t)(v >> 32);
-        }
-        HaloFaces hf = halo_faces(g, k, s);
-        // x faces: bit ly + 16 lz -> half-word l; y faces: bit lx + 16 lz -> half-word l
-        xm = (ld32(hf.lo[0] + (l >> 1)) >> (16 * (l & 1))) & 0xFFFFu;
-        xp = (ld32(hf.hi[0] + (l >> 1)) >> (16 * (l & 1))) & 0xFFFFu;
-        ym = (ld32(hf.lo[1] + (l >> 1)) >> (16 * (l & 1))) & 0xFFFFu;
-        yp = (ld32(hf.hi[1] + (l >> 1)) >> (16 * (l & 1))) & 0xFFFFu;
-        // z faces (bit lx + 16 ly, the layout of a plane): plane 0 needs the face
-        // below, plane 15 the face above; the DPP shifts keep them in those lanes
-        if (l == 0 || l == 15) {
-            const uint32_t *zface = l == 0 ? hf.lo[2] : hf.hi[2];
-#pragma unroll
-            for (int p = 0; p < 8; p += 2) {
-                uint64_t v = ld_words2(zface + p);
-                zf[p] = (uint32_t)v;
-                zf[p + 1] = (uint32_t)(v >> 32);
-            }
-        }
+    for (int p = 0; p < 8; p += 2) {
+        uint64_t v = ld_words2(A + p);
+        r.W[p] = (uint32_t)v;
+        r.W[p + 1] = (uint32_t)(v >> 32);
     }
-    // x halo bits: for word p, bit 0 <- xm bit 2p, bit 16 <- xm bit 2p+1 (and bits 15, 31 for xp)
-    uint32_t Tm = xm | (xm << 15), Tp = xp | (xp << 15);
+    HaloFaces hf = halo_faces(g, k, s, nb);
+    // x faces: bit ly + 16 lz -> half-word l; y faces: bit lx + 16 lz -> half-word l
+    r.xm = ld32(hf.lo[0] + (l >> 1));
+    r.xp = ld32(hf.hi[0] + (l >> 1));
+    r.ym = ld32(hf.lo[1] + (l >> 1));
+    r.yp = ld32(hf.hi[1] + (l >> 1));
+    // z faces (bit lx + 16 ly, the layout of a plane), one word per lane
+    r.zw = ld32((l < 8 ? hf.lo[2] : hf.hi[2]) + (l & 7));
+}
+
+// zrow: this row's 24 LDS words: face below (8), face above (8), zeros (8)
+__device__ __forceinline__ void compute16(const Raw<16> &r, bool valid, int l, uint32_t *zrow, Planes<16> &P,
+                                          uint32_t (&m)[13]) {
+    zrow[l] = r.zw;  // the row's own lanes read these back (same wavefront)
+    const uint32_t *zlo = zrow + (l == 0 ? 0 : 16), *zhi = zrow + (l == 15 ? 8 : 16);
+    const uint32_t sh16 = 16 * (l & 1);
+    const uint32_t xm = (r.xm >> sh16) & 0xFFFFu, xp = (r.xp >> sh16) & 0xFFFFu;
+    const uint32_t ym = (r.ym >> sh16) & 0xFFFFu, yp = (r.yp >> sh16) & 0xFFFFu;
+    // x halo bits: word p needs xm bits 2p, 2p+1 at bits 0, 16 and xp bits 2p, 2p+1 at 15, 31
+    const uint32_t Tm = xm | (xm << 15), Tp = xp | (xp << 15);
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-        uint32_t w = W[p];
-        uint32_t nxm = ((w << 1) & 0xFFFEFFFEu) | ((Tm >> (2 * p)) & 0x00010001u);
-        uint32_t nxp = ((w >> 1) & 0x7FFF7FFFu) | (((Tp >> (2 * p)) & 0x00010001u) << 15);
-        uint32_t nym = p == 0 ? ((w << 16) | ym) : align_hi(w, W[p - 1], 16);
-        uint32_t nyp = p == 7 ? ((yp << 16) | (w >> 16)) : align_hi(W[p + 1], w, 16);
-        uint32_t nzm = dpp<kRowShr1>(zf[p], w);  // plane lz - 1, or the face below at lz = 0
-        uint32_t nzp = dpp<kRowShl1>(zf[p], w);  // plane lz + 1, or the face above at lz = 15
+        const uint32_t w = r.W[p];
+        uint32_t nxm = bop<kSelAC_BnC>(w << 1, Tm >> (2 * p), 0xFFFEFFFEu);
+        uint32_t nxp = bop<kSelAC_BnC>(w >> 1, Tp << (15 - 2 * p), 0x7FFF7FFFu);
+        uint32_t nym = p == 0 ? ((w << 16) | ym) : align_hi(w, r.W[p - 1], 16);
+        uint32_t nyp = p == 7 ? align_hi(yp, w, 16) : align_hi(r.W[p + 1], w, 16);
+        // plane lz -+ 1; the first and last lane take the face word instead
+        uint32_t nzm = dpp0<kRowShr1>(w) | zlo[p];
+        uint32_t nzp = dpp0<kRowShl1>(w) | zhi[p];
         uint32_t o0, o1, o2;
         count6(nxm, nxp, nym, nyp, nzm, nzp, o0, o1, o2);
         P.S[p] = w;
@@ -253,32 +293,36 @@ __device__ __forceinline__ void bin_octant16(const Geom &g, uint32_t k, int s, b
 __device__ __forceinline__ uint32_t spread4(uint32_t nib) {  // bits 0..3 -> bits 0, 8, 16, 24
     return (nib * 0x00204081u) & 0x01010101u;
 }
-__device__ __forceinline__ void bin_octant8(const Geom &g, uint32_t k, int s, bool valid, int l, Planes<8> &P,
-                                            uint32_t (&m)[13]) {
+__device__ __forceinline__ void load8(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb, Raw<8> &r) {
     int lz = l >> 1, p = l & 1;
-    uint32_t w = 0, xm = 0, xp = 0, yface = 0, zface = 0;
-    if (valid) {
-        w = ld32(g.A + ((uint64_t)k * 8 + s) * 16 + l);
-        HaloFaces hf = halo_faces(g, k, s);
-        // x faces: bit ly + 8 lz; rows 4p..4p+3 of plane lz = bits 4l .. 4l + 3
-        xm = (ld32(hf.lo[0] + (l >> 3)) >> (4 * (l & 7))) & 0xFu;
-        xp = (ld32(hf.hi[0] + (l >> 3)) >> (4 * (l & 7))) & 0xFu;
-        // y faces: bit lx + 8 lz = byte lz; the lowest row of p = 0 needs the face below,
-        // the highest row of p = 1 the face above
-        const uint32_t *yf = p == 0 ? hf.lo[1] : hf.hi[1];
-        yface = (ld32(yf + (lz >> 2)) >> (8 * (lz & 3))) & 0xFFu;
-        // z faces: bit lx + 8 ly, word p covers rows 4p .. 4p + 3
-        if (lz == 0) zface = ld32(hf.lo[2] + p);
-        if (lz == 7) zface = ld32(hf.hi[2] + p);
-    }
-    uint32_t nxm = ((w << 1) & 0xFEFEFEFEu) | spread4(xm);
-    uint32_t nxp = ((w >> 1) & 0x7F7F7F7Fu) | (spread4(xp) << 7);
-    uint32_t below = dpp<kRowShr1>(0u, w);  // word l - 1 (row 4p - 1 when p = 1)
-    uint32_t above = dpp<kRowShl1>(0u, w);  // word l + 1 (row 4p + 4 when p = 0)
+    r.w = r.xm = r.xp = r.yface = r.zface = 0;
+    if (!valid) return;
+    r.w = ld32(g.A + ((uint64_t)k * 8 + s) * 16 + l);
+    HaloFaces hf = halo_faces(g, k, s, nb);
+    // x faces: bit ly + 8 lz; rows 4p..4p+3 of plane lz = bits 4l .. 4l + 3
+    r.xm = ld32(hf.lo[0] + (l >> 3));
+    r.xp = ld32(hf.hi[0] + (l >> 3));
+    // y faces: bit lx + 8 lz = byte lz; the lowest row of p = 0 needs the face below,
+    // the highest row of p = 1 the face above
+    r.yface = ld32((p == 0 ? hf.lo[1] : hf.hi[1]) + (lz >> 2));
+    // z faces: bit lx + 8 ly, word p covers rows 4p .. 4p + 3
+    if (lz == 0) r.zface = ld32(hf.lo[2] + p);
+    if (lz == 7) r.zface = ld32(hf.hi[2] + p);
+}
+__device__ __forceinline__ void compute8(const Raw<8> &r, bool valid, int l, uint32_t *, Planes<8> &P,
+                                         uint32_t (&m)[13]) {
+    int lz = l >> 1, p = l & 1;
+    const uint32_t w = r.w;
+    const uint32_t xm = (r.xm >> (4 * (l & 7))) & 0xFu, xp = (r.xp >> (4 * (l & 7))) & 0xFu;
+    const uint32_t yface = (r.yface >> (8 * (lz & 3))) & 0xFFu;
+    uint32_t nxm = bop<kSelAC_BnC>(w << 1, spread4(xm), 0xFEFEFEFEu);
+    uint32_t nxp = bop<kSelAC_BnC>(w >> 1, spread4(xp) << 7, 0x7F7F7F7Fu);
+    uint32_t below = dpp0<kRowShr1>(w);  // word l - 1 (row 4p - 1 when p = 1)
+    uint32_t above = dpp0<kRowShl1>(w);  // word l + 1 (row 4p + 4 when p = 0)
     uint32_t nym = p ? align_hi(w, below, 24) : ((w << 8) | yface);
     uint32_t nyp = p ? ((yface << 24) | (w >> 8)) : align_hi(above, w, 8);
-    uint32_t nzm = dpp<kRowShr2>(zface, w);  // plane lz - 1 (lanes 0, 1 keep the face below)
-    uint32_t nzp = dpp<kRowShl2>(zface, w);  // plane lz + 1 (lanes 14, 15 keep the face above)
+    uint32_t nzm = dpp<kRowShr2>(r.zface, w);  // plane lz - 1 (lanes 0, 1 keep the face below)
+    uint32_t nzp = dpp<kRowShl2>(r.zface, w);  // plane lz + 1 (lanes 14, 15 keep the face above)
     uint32_t o0, o1, o2;
     count6(nxm, nxp, nym, nyp, nzm, nzp, o0, o1, o2);
     P.S[0] = w;
@@ -289,20 +333,41 @@ __device__ __forceinline__ void bin_octant8(const Geom &g, uint32_t k, int s, bo
 }
 
 template <int H>
-__device__ __forceinline__ void bin_octant(const Geom &g, uint32_t k, int s, bool valid, int l, Planes<H> &P,
-                                           uint32_t (&m)[13]) {
-    if constexpr (H == 16) bin_octant16(g, k, s, valid, l, P, m);
-    else bin_octant8(g, k, s, valid, l, P, m);
+__device__ __forceinline__ void load_octant(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
+                                            Raw<H> &r) {
+    if constexpr (H == 16) load16(g, k, s, valid, l, nb, r);
+    else load8(g, k, s, valid, l, nb, r);
+}
+template <int H>
+__device__ __forceinline__ void compute_octant(const Raw<H> &r, bool valid, int l, uint32_t *zrow, Planes<H> &P,
+                                               uint32_t (&m)[13]) {
+    if constexpr (H == 16) compute16(r, valid, l, zrow, P, m);
+    else compute8(r, valid, l, zrow, P, m);
 }
 
 // Inclusive prefix sum over the 16 lanes of a DPP row (lane 15 ends with the
 // row total): four shifted adds, lanes shifted in from outside the row add 0.
 __device__ __forceinline__ uint32_t row_scan(uint32_t v) {
-    v += dpp<kRowShr1>(0u, v);
-    v += dpp<kRowShr2>(0u, v);
-    v += dpp<kRowShr4>(0u, v);
-    v += dpp<kRowShr8>(0u, v);
+    v += dpp0<kRowShr1>(v);
+    v += dpp0<kRowShr2>(v);
+    v += dpp0<kRowShr4>(v);
+    v += dpp0<kRowShr8>(v);
     return v;
+}
+
+// position of the r-th (0-based) set bit of m (r < popcount(m)), by halving
+__device__ __forceinline__ int nth_set_bit(uint32_t m, uint32_t r) {
+    int pos = 0;
+#pragma unroll
+    for (int w = 16; w >= 1; w >>= 1) {
+        uint32_t c = __builtin_popcount(m & ((1u << w) - 1u));
+        if (r >= c) {
+            r -= c;
+            m >>= w;
+            pos += w;
+        }
+    }
+    return pos;
 }
 
 // wall clock (100 MHz) for bounded waits
@@ -311,46 +376,99 @@ __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memr
 }  // namespace
 
 // Workgroup-shared state of the persistent kernel.
-constexpr int kMaxWgDomains = 256;
 struct PersistShared {
-    double r[14];                       // rate table
-    uint32_t mom[kMaxWgDomains][13];    // per domain: the 13 popcount moments of its active octant
-    uint32_t hist[kMaxWgDomains][14];   // per domain: class histogram
-    double acc[kMaxWgDomains][14];      // per domain: running FP64 sums of the frequency line
+    double r[14];                      // rate table
+    uint32_t mom[kMaxWgDomains][13];   // per domain: the 13 popcount moments of its active octant
+    uint32_t hist[kMaxWgDomains][14];  // per domain: class histogram
+    double acc[kMaxWgDomains][14];     // per domain: running FP64 sums of the frequency line
     double rk[kMaxWgDomains];
+    uint32_t zbuf[64][24];             // per row: z face words below (8), above (8), zeros (8)
+    uint32_t nbdom[kMaxWgDomains][6];  // per domain: the neighbour domains -x, +x, -y, +y, -z, +z
+    uint32_t flipq[kMaxWgDomains];     // flips of this cycle: (domain << 16) | (class << 12) | site q
+    uint32_t nflip;
     double rmax;
     int abort;
     uint32_t nbr_bits[6][kMaxGrid / 32];  // neighbour workgroups per direction, as a bitmap
     uint32_t nbr_cnt[6];                  // > kMaxNbr: too many, wait for every workgroup
     uint32_t nbr[6][kMaxNbr];
     long long red[3][16];
+    // observation records whose partials are still to be summed (workgroup 0)
+    uint32_t pend_head, pend_tail;
+    uint64_t pend_cycle[kRecBanks];
+    double pend_t[kRecBanks];
+    uint32_t pend_bank[kRecBanks];
 };
+
+// Sum the partials of the oldest pending record over all workgroups (one
+// wavefront) and append the record.  The caller guarantees every workgroup has
+// stored them.
+__device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch &xs, PersistShared &sh, uint32_t G,
+                                            int lane, uint64_t n0, uint64_t fired0, uint64_t nulls0, int64_t M0,
+                                            int64_t B0) {
+    const uint32_t slot = sh.pend_head % kRecBanks;
+    const int64_t *rp = xs.recp + (uint64_t)sh.pend_bank[slot] * G * 3;
+    long long F = 0, dM = 0, dB = 0;
+    for (uint32_t w = (uint32_t)lane; w < G; w += 64) {
+        F += (long long)ld64((const uint64_t *)&rp[3 * w]);
+        dM += (long long)ld64((const uint64_t *)&rp[3 * w + 1]);
+        dB += (long long)ld64((const uint64_t *)&rp[3 * w + 2]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        F += __shfl_xor(F, o);
+        dM += __shfl_xor(dM, o);
+        dB += __shfl_xor(dB, o);
+    }
+    if (lane == 0) {
+        const uint64_t cyc = sh.pend_cycle[slot];
+        spkmc_record r;
+        r.cycle = cyc;
+        r.fired = fired0 + (uint64_t)F;
+        r.nulls = nulls0 + (uint64_t)g.K * (cyc - n0) - (uint64_t)F;
+        r.t = sh.pend_t[slot];
+        r.M = M0 + dM;
+        r.B = B0 + dB;
+        DevState *st = g.st;
+        g.rec[st->rec_count % g.rec_cap] = r;
+        st->rec_count += 1;
+        sh.pend_head += 1;
+    }
+}
 
 template <int H, int P, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_persistent(Geom g, PersistScratch xs, uint64_t n0, uint64_t ncycles,
                                                      uint32_t obs_every) {
     __shared__ PersistShared sh;
+    constexpr int nthr = BLOCK;
+    constexpr int rows = BLOCK / 16;        // domains per pass
     const int tid = threadIdx.x;
-    const int nthr = BLOCK;
-    const int rows = nthr >> 4;              // domains per pass
     const int row = tid >> 4, l = tid & 15;  // DPP row and lane inside it
     const uint32_t G = gridDim.x, gid = blockIdx.x;
     const uint32_t D = (uint32_t)(rows * P);
     const uint32_t kbase = gid * D;
     const uint32_t nvalid = kbase >= g.K ? 0u : (g.K - kbase < D ? g.K - kbase : D);
+    const bool recorder = gid == 0;
+    const uint64_t n_end = n0 + ncycles;
 
     // neighbour workgroups per direction (0: -x, 1: +x, 2: -y, 3: +y, 4: -z, 5: +z)
     for (uint32_t i = tid; i < 6 * (kMaxGrid / 32); i += nthr) (&sh.nbr_bits[0][0])[i] = 0;
-    if (tid == 0) sh.abort = 0;
+    if (tid == 0) {
+        sh.abort = 0;
+        sh.pend_head = sh.pend_tail = 0;
+    }
     if (tid < 14) sh.r[tid] = g.r[tid];
-    __syncthreads();
+    if (l < 8) sh.zbuf[row][16 + l] = 0;
     for (uint32_t i = tid; i < nvalid * 6; i += nthr) {
-        uint32_t k = kbase + i / 6;
+        uint32_t ldm = i / 6;
         int dir = (int)(i % 6), a = dir >> 1;
-        DomainCoord c = dcoord(k, g.nd);
+        DomainCoord c = dcoord(kbase + ldm, g.nd);
         int kc[3] = {c.kx, c.ky, c.kz};
         kc[a] = (dir & 1) ? wrapp(kc[a], g.nd) : wrapm(kc[a], g.nd);
-        uint32_t owner = dindex(kc[0], kc[1], kc[2], g.nd) / D;
+        sh.nbdom[ldm][dir] = dindex(kc[0], kc[1], kc[2], g.nd);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < nvalid * 6; i += nthr) {
+        int dir = (int)(i % 6);
+        uint32_t owner = sh.nbdom[i / 6][dir] / D;
         if (owner != gid) atomicOr(&sh.nbr_bits[dir][owner >> 5], 1u << (owner & 31));
     }
     __syncthreads();
@@ -373,10 +491,9 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(Geom g, PersistScratch xs,
     double t = st->t;  // every workgroup advances the same clock
     long long myF = 0, mydM = 0, mydB = 0;  // this thread's share since launch start
     uint32_t rec_index = 0;                  // records produced in this launch
-    bool rec_pending = false;
     int prev_colour = -1;
 
-    for (uint64_t n = n0; n < n0 + ncycles; ++n) {
+    for (uint64_t n = n0; n < n_end; ++n) {
         CycleDraw cd = cycle_draw(g.seed, n);
         const int s = cd.colour;
 
@@ -406,25 +523,28 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(Geom g, PersistScratch xs,
         }
         prev_colour = s;
 
-        // --- steps 1 and 4a: class planes and histograms of the active octants
+        // --- steps 1 and 4a: class planes and moments of the active octants
         Planes<H> pl[P];
+        Raw<H> raw[2];
+        load_octant<H>(g, kbase + (uint32_t)row, s, (uint32_t)row < nvalid, l, sh.nbdom[row], raw[0]);
 #pragma unroll
         for (int pp = 0; pp < P; ++pp) {
             uint32_t ld = (uint32_t)(pp * rows + row);
-            uint32_t k = kbase + ld;
             bool valid = ld < nvalid;
+            if (pp + 1 < P) {  // next pass's words in flight while this pass computes
+                uint32_t ldn = ld + (uint32_t)rows;
+                load_octant<H>(g, kbase + ldn, s, ldn < nvalid, l, sh.nbdom[ldn < nvalid ? ldn : 0], raw[(pp + 1) & 1]);
+            }
             uint32_t m[13];
 #pragma unroll
             for (int i = 0; i < 13; ++i) m[i] = 0;
-            bin_octant<H>(g, k, s, valid, l, pl[pp], m);
+            compute_octant<H>(raw[pp & 1], valid, l, sh.zbuf[row], pl[pp], m);
 #pragma unroll
             for (int i = 0; i < 13; ++i) m[i] = row_scan(m[i]);
             if (l == 15) {
 #pragma unroll
                 for (int i = 0; i < 13; ++i) sh.mom[ld][i] = m[i];
             }
-            // keep the passes apart: interleaving them only adds live registers
-            __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
         // step 1: histogram and frequency line of every domain of the workgroup,
@@ -451,27 +571,43 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(Geom g, PersistScratch xs,
             for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
             // bank n & 1 holds cycles n - 2 and n; the generation bit tells them apart
             uint64_t *bank = xs.slot + (n & 1) * (uint64_t)G;
-            const uint64_t parity = ((n >> 1) & 1) << 63;
-            if (tid == 0) st64(&bank[gid], double_to_bits(v) | parity);
-            // poll every slot until all carry this cycle's parity
+            const uint64_t gen = ((n >> 1) & 1) << 63;
+            if (tid == 0) st64(&bank[gid], double_to_bits(v) | gen);
+            // workgroup 0 sums a record stored two or more cycles ago while it waits
+            if (recorder && sh.pend_head != sh.pend_tail && sh.pend_cycle[sh.pend_head % kRecBanks] + 2 <= n + 1)
+                emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
+            // poll every slot until all carry this cycle's generation: one round of
+            // loads for a block of slots, then only the ones not yet there
             uint64_t start = now_ticks();
             double best = 0.0;
-            for (uint32_t base = 0; base < G; base += 64) {
-                uint32_t w = base + tid;
-                uint64_t sv = parity;
-                if (w < G) {
-                    sv = ld64(&bank[w]);
-                    while ((sv & (1ull << 63)) != parity) {
-                        __builtin_amdgcn_s_sleep(1);
-                        if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
-                            atomicOr(&st->error, kErrBarrierTimeout);
-                            sh.abort = 1;
-                            break;
+            constexpr int kSlotsPerLane = 4;  // 256 slots per round of the first wave
+            for (uint32_t base = 0; base < G && !sh.abort; base += 64 * kSlotsPerLane) {
+                uint64_t sv[kSlotsPerLane];
+#pragma unroll
+                for (int i = 0; i < kSlotsPerLane; ++i) {
+                    uint32_t w = base + (uint32_t)i * 64 + tid;
+                    sv[i] = w < G ? ld64(&bank[w]) : gen;
+                }
+                for (;;) {
+                    bool all = true;
+#pragma unroll
+                    for (int i = 0; i < kSlotsPerLane; ++i) {
+                        uint32_t w = base + (uint32_t)i * 64 + tid;
+                        if ((sv[i] & (1ull << 63)) != gen) {
+                            all = false;
+                            sv[i] = ld64(&bank[w]);
                         }
-                        sv = ld64(&bank[w]);
+                    }
+                    if (__all(all)) break;
+                    __builtin_amdgcn_s_sleep(1);
+                    if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
+                        atomicOr(&st->error, kErrBarrierTimeout);
+                        sh.abort = 1;
+                        break;
                     }
                 }
-                best = fmax(best, bits_to_double(sv & ~(1ull << 63)));
+#pragma unroll
+                for (int i = 0; i < kSlotsPerLane; ++i) best = fmax(best, bits_to_double(sv[i] & ~(1ull << 63)));
             }
             for (int o = 32; o > 0; o >>= 1) best = fmax(best, __shfl_xor(best, o));
             if (tid == 0) sh.rmax = best;
@@ -480,103 +616,85 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(Geom g, PersistScratch xs,
         if (sh.abort) break;
         const double Rmax = sh.rmax;
 
-        // pending record of the previous cycle: every workgroup has finished it
-        if (rec_pending && gid == 0 && tid == 0 && g.rec_cap) {
-            long long F = 0, dM = 0, dB = 0;
-            const int64_t *rp = xs.recp + (uint64_t)((rec_index - 1) & 1) * G * 3;
-            for (uint32_t w = 0; w < G; ++w) {
-                F += (long long)ld64((const uint64_t *)&rp[3 * w]);
-                dM += (long long)ld64((const uint64_t *)&rp[3 * w + 1]);
-                dB += (long long)ld64((const uint64_t *)&rp[3 * w + 2]);
-            }
-            spkmc_record r;
-            r.cycle = n;  // the state after cycle n - 1
-            r.fired = fired0 + (uint64_t)F;
-            r.nulls = nulls0 + (uint64_t)g.K * (n - n0) - (uint64_t)F;
-            r.t = t;
-            r.M = M0 + dM;
-            r.B = B0 + dB;
-            g.rec[st->rec_count % g.rec_cap] = r;
-            st->rec_count += 1;
+        // --- steps 3, 4 and 4b: event or null in every domain
+        if (tid == 0) sh.nflip = 0;
+        // lane pp of each row draws for the row's domain of pass pp
+        U4 dw;
+        {
+            const uint32_t kd = kbase + (uint32_t)((l < P ? l : 0) * rows + row);
+            dw = philox10((uint32_t)n, (uint32_t)(n >> 32), kd, (uint32_t)s, g.seed);
         }
-        rec_pending = false;
-
-        // --- steps 3, 4 and 4b: event or null in every domain, then the flip
+        __syncthreads();
 #pragma unroll
         for (int pp = 0; pp < P; ++pp) {
-            uint32_t ld = (uint32_t)(pp * rows + row);
-            uint32_t k = kbase + ld;
-            bool valid = ld < nvalid;
-            int cs = -1;
-            uint32_t j = 0;
-            if (valid) {
-                U4 dw = philox10((uint32_t)n, (uint32_t)(n >> 32), k, (uint32_t)s, g.seed);
-                double target = unit53(dw.x, dw.y) * Rmax;
-                // first class whose running sum exceeds the target; none: the null event
-                for (int c = 0; c < 14; ++c)
-                    if (target < sh.acc[ld][c]) { cs = c; break; }
-                if (cs >= 0) j = mul_index(dw.z, sh.hist[ld][cs]);
-            }
+            const uint32_t ld = (uint32_t)(pp * rows + row);
+            const bool valid = ld < nvalid;
+            const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
+            const double target = unit53(ux, uy) * Rmax;
+            // first class whose running sum exceeds the target (lane c of the row
+            // tests class c); none: the null event
+            const bool hit = valid && l < 14 && target < sh.acc[ld][l < 14 ? l : 13];
+            const uint64_t bal = __ballot(hit);
+            const uint32_t rowbits = (uint32_t)(bal >> (16 * (row & 3))) & 0xFFFFu;
+            const int cs = rowbits ? __builtin_ctz(rowbits) : -1;
+            const uint32_t j = cs >= 0 ? mul_index(uz, sh.hist[ld][cs]) : 0u;
             // class cs as (spin, n_up pattern): up spin: n_up = a; down spin: n_up = 6 - a
-            uint32_t es = 0, e0 = 0, e1 = 0, e2 = 0;
-            int a = 0;
-            if (cs >= 0) {
-                int up = cs >= 7;
-                a = cs % 7;
-                int v = up ? a : 6 - a;
-                es = up ? 0xFFFFFFFFu : 0u;
-                e0 = (v & 1) ? 0xFFFFFFFFu : 0u;
-                e1 = (v & 2) ? 0xFFFFFFFFu : 0u;
-                e2 = (v & 4) ? 0xFFFFFFFFu : 0u;
-            }
+            const int up = cs >= 7, aa = cs >= 0 ? cs % 7 : 0, v = up ? aa : 6 - aa;
+            const uint32_t es = up ? 0u : 0xFFFFFFFFu;  // bits that must be 0 after the xor
+            const uint32_t e0 = (v & 1) ? 0u : 0xFFFFFFFFu, e1 = (v & 2) ? 0u : 0xFFFFFFFFu;
+            const uint32_t e2 = (v & 4) ? 0u : 0xFFFFFFFFu;
             constexpr int WPL = Planes<H>::W;
             uint32_t mk[WPL];
             uint32_t cnt = 0;
 #pragma unroll
             for (int p = 0; p < WPL; ++p) {
-                uint32_t miss = (pl[pp].S[p] ^ es) | (pl[pp].b0[p] ^ e0) | (pl[pp].b1[p] ^ e1) | (pl[pp].b2[p] ^ e2);
-                mk[p] = cs >= 0 ? ~miss : 0u;
+                // sites of class cs: every plane equal to the class pattern
+                uint32_t m2 = bop<kAnd3>(pl[pp].S[p] ^ es, pl[pp].b0[p] ^ e0, pl[pp].b1[p] ^ e1);
+                mk[p] = cs >= 0 ? (m2 & (pl[pp].b2[p] ^ e2)) : 0u;
                 cnt += __builtin_popcount(mk[p]);
             }
             // inclusive prefix over the 16 lanes of the row (canonical order = lane order)
-            uint32_t incl = row_scan(cnt);
-            uint32_t excl = incl - cnt;
+            const uint32_t incl = row_scan(cnt);
+            const uint32_t excl = incl - cnt;
             if (cs >= 0 && j >= excl && j < incl) {
-                uint32_t r = j - excl;
-                int wsel = 0;
+                uint32_t r = j - excl, msk = 0;
+                int wsel = WPL;
 #pragma unroll
                 for (int p = 0; p < WPL; ++p) {
                     uint32_t c = __builtin_popcount(mk[p]);
-                    if (wsel == p && r >= c) { r -= c; wsel = p + 1; }
+                    if (wsel == WPL) {
+                        if (r < c) { wsel = p; msk = mk[p]; }
+                        else r -= c;
+                    }
                 }
-                uint32_t msk = 0;
-#pragma unroll
-                for (int p = 0; p < WPL; ++p)
-                    if (p == wsel) msk = mk[p];
-                for (uint32_t i = 0; i < r; ++i) msk &= msk - 1;
-                if (msk == 0) {  // the counts disagree with the masks: report, flip nothing
+                if (wsel == WPL || msk == 0) {  // counts disagree with masks: report, flip nothing
                     atomicOr(&st->error, kErrSelect);
-                    continue;
+                } else {
+                    const uint32_t q = (uint32_t)(l * WPL + wsel) * 32 + (uint32_t)nth_set_bit(msk, r);
+                    const uint32_t slot = atomicAdd(&sh.nflip, 1u);
+                    sh.flipq[slot] = (ld << 16) | ((uint32_t)cs << 12) | q;
                 }
-                int bit = __builtin_ctz(msk);
-                uint32_t wq = (uint32_t)(l * WPL + wsel);  // word index inside the octant
-                uint32_t q = wq * 32 + (uint32_t)bit;
-                uint32_t *A = g.A + ((uint64_t)k * 8 + s) * g.wpo;
-                uint32_t old = flip_word(A + wq, 1u << bit);
-                int sold = ((old >> bit) & 1u) ? 1 : -1;
-                uint32_t lx = q % H, ly = (q / H) % H, lz = q / (H * H);
-                uint32_t *F = g.F + ((uint64_t)k * 8 + s) * g.fwpo;
-                const uint32_t e = H - 1, h2 = H * H;
-                if (lx == 0) { uint32_t b = ly + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
-                if (lx == e) { uint32_t b = h2 + ly + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
-                if (ly == 0) { uint32_t b = 2 * h2 + lx + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
-                if (ly == e) { uint32_t b = 3 * h2 + lx + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
-                if (lz == 0) { uint32_t b = 4 * h2 + lx + H * ly; flip_word(F + (b >> 5), 1u << (b & 31)); }
-                if (lz == e) { uint32_t b = 5 * h2 + lx + H * ly; flip_word(F + (b >> 5), 1u << (b & 31)); }
-                myF += 1;
-                mydM += -2 * sold;
-                mydB += 12 - 4 * a;
             }
+        }
+        __syncthreads();
+        // --- the flips of this cycle, one thread each
+        for (uint32_t i = tid; i < sh.nflip; i += nthr) {
+            const uint32_t f = sh.flipq[i];
+            const uint32_t ld = f >> 16, cs = (f >> 12) & 15u, q = f & 0xFFFu;
+            const uint32_t k = kbase + ld;
+            flip_word(g.A + ((uint64_t)k * 8 + s) * g.wpo + (q >> 5), 1u << (q & 31));
+            const uint32_t lx = q % H, ly = (q / H) % H, lz = q / (H * H);
+            uint32_t *F = g.F + ((uint64_t)k * 8 + s) * g.fwpo;
+            constexpr uint32_t e = H - 1, h2 = H * H;
+            if (lx == 0) { uint32_t b = ly + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
+            if (lx == e) { uint32_t b = h2 + ly + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
+            if (ly == 0) { uint32_t b = 2 * h2 + lx + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
+            if (ly == e) { uint32_t b = 3 * h2 + lx + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
+            if (lz == 0) { uint32_t b = 4 * h2 + lx + H * ly; flip_word(F + (b >> 5), 1u << (b & 31)); }
+            if (lz == e) { uint32_t b = 5 * h2 + lx + H * ly; flip_word(F + (b >> 5), 1u << (b & 31)); }
+            myF += 1;
+            mydM += cs >= 7 ? -2 : 2;              // the class carries the old spin
+            mydB += 12 - 4 * (long long)(cs % 7);  // and its aligned count
         }
 
         // --- step 5: the clock, identical in every workgroup
@@ -589,8 +707,9 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(Geom g, PersistScratch xs,
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
 
-        const bool record = obs_every && ((n + 1) % obs_every) == 0;
-        if (record || n + 1 == n0 + ncycles) {
+        const bool last = n + 1 == n_end;
+        const bool record = obs_every && ((n + 1) % obs_every) == 0 && g.rec_cap;
+        if (record || last) {
             // workgroup totals since launch start
             long long F = myF, dM = mydM, dB = mydB;
             for (int o = 32; o > 0; o >>= 1) {
@@ -611,36 +730,78 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(Geom g, PersistScratch xs,
                     dM += sh.red[1][w];
                     dB += sh.red[2][w];
                 }
-                if (n + 1 == n0 + ncycles) {
+                if (last) {
                     // end of the launch: fold this workgroup's share into the totals
                     atomicAdd((unsigned long long *)&st->fired, (unsigned long long)F);
-                    atomicAdd((unsigned long long *)&st->nulls, (unsigned long long)((long long)nvalid * (long long)ncycles - F));
+                    atomicAdd((unsigned long long *)&st->nulls,
+                              (unsigned long long)((long long)nvalid * (long long)ncycles - F));
                     atomicAdd((unsigned long long *)&st->M, (unsigned long long)dM);
                     atomicAdd((unsigned long long *)&st->B, (unsigned long long)dB);
                 } else {
-                    int64_t *rp = xs.recp + (uint64_t)(rec_index & 1) * G * 3;
+                    const uint32_t bank = rec_index % kRecBanks;
+                    int64_t *rp = xs.recp + (uint64_t)bank * G * 3;
                     st64((uint64_t *)&rp[3 * gid], (uint64_t)F);
                     st64((uint64_t *)&rp[3 * gid + 1], (uint64_t)dM);
                     st64((uint64_t *)&rp[3 * gid + 2], (uint64_t)dB);
+                    if (recorder) {
+                        const uint32_t slot = sh.pend_tail % kRecBanks;
+                        sh.pend_cycle[slot] = n + 1;
+                        sh.pend_t[slot] = t;
+                        sh.pend_bank[slot] = bank;
+                        sh.pend_tail += 1;
+                    }
                 }
             }
-            if (record && n + 1 != n0 + ncycles) {
-                rec_pending = true;
-                rec_index += 1;
-            }
+            if (record && !last) rec_index += 1;
         }
         if (tid == 0) {
             __builtin_amdgcn_s_waitcnt(0);
             st64(&xs.flag[gid], n + 1);
         }
     }
-    if (gid == 0 && tid == 0) {
-        st->t = t;
-        st->cycle = n0 + ncycles;
+
+    // end of the launch: workgroup 0 waits for every workgroup to finish, then
+    // appends the records still pending and the record of the last cycle
+    if (recorder) {
+        if (tid < 64 && !sh.abort) {
+            uint64_t start = now_ticks();
+            for (uint32_t w = tid; w < G; w += 64)
+                while (ld64(&xs.flag[w]) < n_end) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
+                        atomicOr(&st->error, kErrFlagTimeout);
+                        sh.abort = 1;
+                        break;
+                    }
+                }
+        }
+        __syncthreads();
+        if (tid < 64 && !sh.abort) {
+            while (sh.pend_head != sh.pend_tail) {
+                emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (tid == 0) {
+                st->t = t;
+                st->cycle = n_end;
+                if (obs_every && (n_end % obs_every) == 0 && g.rec_cap) {
+                    spkmc_record r;
+                    r.cycle = n_end;
+                    r.fired = ld64(&st->fired);
+                    r.nulls = ld64(&st->nulls);
+                    r.t = t;
+                    r.M = (int64_t)ld64((const uint64_t *)&st->M);
+                    r.B = (int64_t)ld64((const uint64_t *)&st->B);
+                    g.rec[st->rec_count % g.rec_cap] = r;
+                    st->rec_count += 1;
+                }
+            }
+        }
     }
 }
 
-// Before a launch: slots carry the parity of the previous cycle, flags the start cycle.
+// Before a launch: slots carry the generation of no cycle of this launch yet,
+// flags the start cycle.
 __global__ void k_persistent_prep(PersistScratch xs, uint32_t G, uint64_t n0) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < G) {
@@ -650,47 +811,30 @@ __global__ void k_persistent_prep(PersistScratch xs, uint32_t G, uint64_t n0) {
     }
 }
 
-// After a launch: the record of the last cycle, from the final totals.
-__global__ void k_persistent_finish(Geom g, uint64_t n_end, uint32_t obs_every) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    DevState *st = g.st;
-    if (obs_every && (n_end % obs_every) == 0 && g.rec_cap) {
-        spkmc_record r;
-        r.cycle = n_end;
-        r.fired = st->fired;
-        r.nulls = st->nulls;
-        r.t = st->t;
-        r.M = st->M;
-        r.B = st->B;
-        g.rec[st->rec_count % g.rec_cap] = r;
-        st->rec_count += 1;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-// Launch shapes: h = 16 keeps 4 passes of 32 domains in registers with 512
-// threads (two waves per SIMD, 256 registers each); h = 8 needs 4 registers per
-// pass and runs 1024 threads.
+// Launch shapes: h = 16 keeps up to 4 passes of 32 domains in registers with
+// 512 threads (two waves per SIMD, 256 registers each); h = 8 needs 4
+// registers per pass and runs 1024 threads.
 template <int H, int P, int BLOCK>
 static void *kernel_ptr() {
     return reinterpret_cast<void *>(&k_persistent<H, P, BLOCK>);
 }
 static void *select_kernel(int h, int P, int block) {
-    if (h == 16) {
-        if (block == 512) return P == 1 ? kernel_ptr<16, 1, 512>() : P == 2 ? kernel_ptr<16, 2, 512>() : kernel_ptr<16, 4, 512>();
-        return nullptr;
-    }
-    if (block == 1024) return P == 1 ? kernel_ptr<8, 1, 1024>() : P == 2 ? kernel_ptr<8, 2, 1024>() : kernel_ptr<8, 4, 1024>();
-    if (block == 256) return P == 1 ? kernel_ptr<8, 1, 256>() : nullptr;
+    if (h == 16 && block == 512)
+        return P == 1 ? kernel_ptr<16, 1, 512>() : P == 2 ? kernel_ptr<16, 2, 512>() : kernel_ptr<16, 4, 512>();
+    if (h == 8 && block == 1024)
+        return P == 1 ? kernel_ptr<8, 1, 1024>() : P == 2 ? kernel_ptr<8, 2, 1024>() : kernel_ptr<8, 4, 1024>();
     return nullptr;
 }
 
 bool persistent_supported(const Geom &g, const spkmc_params &p, std::string &why) {
     if (g.layout != SPKMC_LAYOUT_PACKED) { why = "needs the PACKED layout"; return false; }
     if (g.h != 8 && g.h != 16) { why = "needs an octant edge of 8 or 16 (domain 16 or 32)"; return false; }
-    if (p.wg_domains && p.wg_domains != (g.h == 16 ? 32 : 64) * (p.wg_domains / (g.h == 16 ? 32 : 64))) {
+    const int rows = g.h == 16 ? 32 : 64;
+    const int pc = p.wg_domains / rows;
+    if (p.wg_domains && (p.wg_domains % rows || pc > 4 || (pc & (pc - 1)))) {
         why = "wg_domains must be 32, 64 or 128 (h = 16) or 64, 128 or 256 (h = 8)";
         return false;
     }
@@ -708,9 +852,7 @@ hipError_t persistent_configure(const Geom &g, const spkmc_params &p, int &grid,
     int P = 0;
     block = rows * 16;
     if (p.wg_domains) {
-        for (int Pc : {1, 2, 4})
-            if (rows * Pc == p.wg_domains) P = Pc;
-        if (!P) return hipErrorInvalidValue;
+        P = p.wg_domains / rows;
     } else {
         // the fewest passes that keep every workgroup resident (one per CU at most)
         P = 1;
@@ -728,6 +870,8 @@ hipError_t persistent_configure(const Geom &g, const spkmc_params &p, int &grid,
     wg_domains = (int)D;
     return hipSuccess;
 }
+
+uint64_t persistent_scratch_words(uint64_t K) { return kScratchWordsPerWg * (K / 16 + 2) + 16; }
 
 static PersistScratch scratch_of(const Geom &g, int G) {
     PersistScratch xs;
@@ -748,10 +892,7 @@ hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint3
     if (e != hipSuccess) return e;
     Geom gg = g;
     void *args[] = {&gg, &xs, &n0, &ncycles, &obs_every};
-    e = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(block), args, 0, stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_persistent_finish, dim3(1), dim3(64), 0, stream, gg, n0 + ncycles, obs_every);
-    return hipGetLastError();
+    return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(block), args, 0, stream);
 }
 
 }  // namespace spkmc

@@ -18,6 +18,7 @@ bool persistent_supported(const Geom &g, const spkmc_params &p, std::string &why
 hipError_t persistent_configure(const Geom &g, const spkmc_params &p, int &grid, int &block, int &wg_domains);
 hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid,
                              int block, int wg_domains, hipStream_t stream);
+uint64_t persistent_scratch_words(uint64_t K);
 }  // namespace spkmc
 
 using namespace spkmc;
@@ -111,8 +112,8 @@ static LayoutPlan plan(const spkmc_params *p) {
     lp.off_Rk = o; o = align256(o + K * 8);
     lp.off_hist = o; o = align256(o + K * 64);
     lp.off_flip = o; o = align256(o + K * 8);
-    // persistent engine: at most K / 16 + 1 workgroups (16 domains or more each), 9 words each
-    lp.off_sync = o; o = align256(o + (9 * (K / 16 + 2) + 16) * 8);
+    // persistent engine: slots, flags and record partials of its workgroups
+    lp.off_sync = o; o = align256(o + persistent_scratch_words(K) * 8);
     lp.off_spin = o;
     if (p->layout == SPKMC_LAYOUT_INT8) {
         o = align256(o + N);
