@@ -63,6 +63,28 @@ def calibrate_copy(mib):
     print(json.dumps({"calibrate_copy_bytes": n, "copies": 3, "read_bytes_per_copy": n, "write_bytes_per_copy": n}))
 
 
+def measured_traffic(workload_name, steps):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary of this kernel and workload (each scaled by the reading of a plain
+    copy of known size); None if there is none or the kernel source changed
+    since the counters were taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")):
+        with open(path) as f:
+            rec = json.load(f)
+        if rec.get("workload") != workload_name:
+            continue
+        m = hashlib.sha256()
+        for name in rec["source_files"]:
+            with open(os.path.join(ROOT, name), "rb") as f:
+                m.update(f.read())
+        if m.hexdigest()[:16] != rec["source_hash"]:
+            return None, None
+        return rec["hbm_bytes_per_cycle"] * steps, rec
+    return None, None
+
+
 def cpu_baseline(w, cycles):
     """The oracle as it stands, single-threaded, on a bounded sample of the
     workload: `cycles` spkMC cycles of the full lattice (initialisation not timed)."""
@@ -128,6 +150,9 @@ def main():
     bytes_cycle = info["bytes_per_cycle"]
     launches = 1 if info["engine"] == spkmc.ENGINES["persistent"] else 3 * args.steps
     achieved = bytes_cycle * args.steps / secs / 1e9
+    traffic, traffic_rec = (None, None)
+    if launches == 1:
+        traffic, traffic_rec = measured_traffic(w["name"], args.steps)
     out = {
         "metric": METRIC,
         "value": value,
@@ -151,10 +176,11 @@ def main():
         "wall_s": wall,
         "sim_time": [s0[3], s1[3]],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "spkmc_persistent" if launches == 1 else "whole cycle (3 launches)",
                      "bytes_per_cycle": bytes_cycle, "launches": launches,
-                     "avg_launch_ms": gpu_ms / launches},
+                     "avg_launch_ms": gpu_ms / launches,
+                     "traffic_source": None if traffic is None else "profiles/persistent_L1024_d32_traffic.json"},
     }
     if not args.no_cpu_baseline:
         cyc = args.cpu_cycles or (3 if w["L"] >= 1024 else 20 if w["L"] >= 512 else 2000)
