@@ -181,6 +181,34 @@ spkmc_status spkmc_load(spkmc_ctx *ctx, const void *host, size_t n);
 /* Launch shape and sizes of a context. */
 spkmc_status spkmc_query(const spkmc_ctx *ctx, spkmc_info *out);
 
+/* ------------------------------------------------------------------------- */
+/* Batches: many independent lattices in one persistent launch.               */
+/* ------------------------------------------------------------------------- */
+typedef struct spkmc_batch_info {
+    int32_t grid;        /* workgroups of the launch                               */
+    int32_t block;       /* threads per workgroup                                  */
+    int32_t wg_domains;  /* domains per workgroup                                  */
+    int32_t h;           /* octant edge shared by the lattices                     */
+    uint64_t lattices;   /* lattices in the launch (those with ncycles > 0)         */
+    uint64_t domains;    /* sum of their domain counts                             */
+} spkmc_batch_info;
+
+/* Device workspace bytes spkmc_run_batch needs for n lattices. */
+size_t spkmc_batch_workspace_bytes(size_t n);
+
+/* Run ncycles[i] cycles (0 = skip) on each of n contexts in one cooperative
+ * launch on their common stream.  The lattices stay independent: each keeps its
+ * own clock, R_max, random streams and records, and the result of every
+ * lattice is bit-identical to running it alone with spkmc_run.  All contexts
+ * must use the PACKED layout with the same octant edge (8 or 16) and the same
+ * stream, and the launch must fit on the device at once (E_UNSUPPORTED
+ * otherwise: split the batch).  wg_domains: domains per workgroup (0 = the
+ * fewest passes that fit).  dev_workspace: spkmc_batch_workspace_bytes(n)
+ * bytes of device memory owned by the caller; it must stay untouched until
+ * the launch has finished.  info (may be NULL) receives the launch shape. */
+spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
+                             int32_t wg_domains, void *dev_workspace, size_t ws_bytes, spkmc_batch_info *info);
+
 /* Message of the last failure on ctx (ctx == NULL: of the last failed call
  * that had no context on this thread).  Never NULL. */
 const char *spkmc_last_error(const spkmc_ctx *ctx);

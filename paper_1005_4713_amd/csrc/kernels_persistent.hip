@@ -60,6 +60,21 @@ struct PersistScratch {
 };
 constexpr uint64_t kScratchWordsPerWg = 2 + 1 + 3 * kRecBanks;
 
+}  // namespace
+
+// One lattice of a persistent launch: its geometry and buffers, its sync
+// scratch, the cycles to run, and its range of workgroups in the launch.
+struct Replica {
+    Geom g;
+    PersistScratch xs;
+    uint64_t n0, ncycles;
+    uint32_t obs_every;
+    uint32_t first_wg, G;  // workgroups first_wg .. first_wg + G - 1 run this lattice
+    uint32_t pad;
+};
+
+namespace {
+
 __device__ __forceinline__ uint32_t ld32(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -435,14 +450,16 @@ __device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch 
 }
 
 template <int H, int P, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) k_persistent(Geom g, PersistScratch xs, uint64_t n0, uint64_t ncycles,
-                                                     uint32_t obs_every) {
-    __shared__ PersistShared sh;
+__device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t gid, PersistShared &sh) {
+    const Geom &g = R.g;
+    const PersistScratch &xs = R.xs;
+    const uint64_t n0 = R.n0, ncycles = R.ncycles;
+    const uint32_t obs_every = R.obs_every;
     constexpr int nthr = BLOCK;
     constexpr int rows = BLOCK / 16;        // domains per pass
     const int tid = threadIdx.x;
     const int row = tid >> 4, l = tid & 15;  // DPP row and lane inside it
-    const uint32_t G = gridDim.x, gid = blockIdx.x;
+    const uint32_t G = R.G;
     const uint32_t D = (uint32_t)(rows * P);
     const uint32_t kbase = gid * D;
     const uint32_t nvalid = kbase >= g.K ? 0u : (g.K - kbase < D ? g.K - kbase : D);
@@ -800,15 +817,44 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(Geom g, PersistScratch xs,
     }
 }
 
+// One lattice: the descriptor by value.
+template <int H, int P, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_persistent(Replica R) {
+    __shared__ PersistShared sh;
+    persistent_body<H, P, BLOCK>(R, blockIdx.x, sh);
+}
+
+// Many independent lattices in one launch: each workgroup finds its lattice by
+// its workgroup index; lattices never wait for one another.
+template <int H, int P, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_persistent_batch(const Replica *__restrict__ reps, uint32_t nrep) {
+    __shared__ PersistShared sh;
+    uint32_t lo = 0, hi = nrep;  // last replica with first_wg <= blockIdx.x
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (reps[mid].first_wg <= blockIdx.x) lo = mid;
+        else hi = mid;
+    }
+    // the index is the same in every lane: keep the descriptor in scalar registers
+    const Replica &R = reps[__builtin_amdgcn_readfirstlane(lo)];
+    if (blockIdx.x >= R.first_wg + R.G) return;  // a spare workgroup past the last lattice
+    persistent_body<H, P, BLOCK>(R, blockIdx.x - R.first_wg, sh);
+}
+
 // Before a launch: slots carry the generation of no cycle of this launch yet,
 // flags the start cycle.
+__device__ __forceinline__ void prep_one(const PersistScratch &xs, uint32_t G, uint64_t n0, uint32_t i) {
+    // bank b first serves cycle nb (n0 or n0 + 1, nb & 1 == b): mark it "not yet"
+    for (uint64_t nb = n0; nb < n0 + 2; ++nb) xs.slot[(nb & 1) * G + i] = (((nb >> 1) + 1) & 1) << 63;
+    xs.flag[i] = n0;
+}
 __global__ void k_persistent_prep(PersistScratch xs, uint32_t G, uint64_t n0) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < G) {
-        // bank b first serves cycle nb (n0 or n0 + 1, nb & 1 == b): mark it "not yet"
-        for (uint64_t nb = n0; nb < n0 + 2; ++nb) xs.slot[(nb & 1) * G + i] = (((nb >> 1) + 1) & 1) << 63;
-        xs.flag[i] = n0;
-    }
+    if (i < G) prep_one(xs, G, n0, i);
+}
+__global__ void k_persistent_prep_batch(const Replica *__restrict__ reps, uint32_t nrep) {
+    for (uint32_t r = blockIdx.x; r < nrep; r += gridDim.x)
+        for (uint32_t i = threadIdx.x; i < reps[r].G; i += blockDim.x) prep_one(reps[r].xs, reps[r].G, reps[r].n0, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -818,14 +864,17 @@ __global__ void k_persistent_prep(PersistScratch xs, uint32_t G, uint64_t n0) {
 // 512 threads (two waves per SIMD, 256 registers each); h = 8 needs 4
 // registers per pass and runs 1024 threads.
 template <int H, int P, int BLOCK>
-static void *kernel_ptr() {
-    return reinterpret_cast<void *>(&k_persistent<H, P, BLOCK>);
+static void *kernel_ptr(bool batch) {
+    return batch ? reinterpret_cast<void *>(&k_persistent_batch<H, P, BLOCK>)
+                 : reinterpret_cast<void *>(&k_persistent<H, P, BLOCK>);
 }
-static void *select_kernel(int h, int P, int block) {
+static void *select_kernel(int h, int P, int block, bool batch = false) {
     if (h == 16 && block == 512)
-        return P == 1 ? kernel_ptr<16, 1, 512>() : P == 2 ? kernel_ptr<16, 2, 512>() : kernel_ptr<16, 4, 512>();
+        return P == 1 ? kernel_ptr<16, 1, 512>(batch) : P == 2 ? kernel_ptr<16, 2, 512>(batch)
+                                                               : kernel_ptr<16, 4, 512>(batch);
     if (h == 8 && block == 1024)
-        return P == 1 ? kernel_ptr<8, 1, 1024>() : P == 2 ? kernel_ptr<8, 2, 1024>() : kernel_ptr<8, 4, 1024>();
+        return P == 1 ? kernel_ptr<8, 1, 1024>(batch) : P == 2 ? kernel_ptr<8, 2, 1024>(batch)
+                                                               : kernel_ptr<8, 4, 1024>(batch);
     return nullptr;
 }
 
@@ -873,7 +922,7 @@ hipError_t persistent_configure(const Geom &g, const spkmc_params &p, int &grid,
 
 uint64_t persistent_scratch_words(uint64_t K) { return kScratchWordsPerWg * (K / 16 + 2) + 16; }
 
-static PersistScratch scratch_of(const Geom &g, int G) {
+PersistScratch scratch_of(const Geom &g, int G) {
     PersistScratch xs;
     xs.slot = g.sync;
     xs.flag = g.sync + 2 * (uint64_t)G;
@@ -890,8 +939,94 @@ hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint3
     hipLaunchKernelGGL(k_persistent_prep, dim3((grid + 255) / 256), dim3(256), 0, stream, xs, (uint32_t)grid, n0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    Geom gg = g;
-    void *args[] = {&gg, &xs, &n0, &ncycles, &obs_every};
+    Replica R;
+    R.g = g;
+    R.xs = xs;
+    R.n0 = n0;
+    R.ncycles = ncycles;
+    R.obs_every = obs_every;
+    R.first_wg = 0;
+    R.G = (uint32_t)grid;
+    R.pad = 0;
+    void *args[] = {&R};
+    return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(block), args, 0, stream);
+}
+
+// ---------------------------------------------------------------------------
+// batches: one cooperative launch over several lattices of the same octant edge
+// ---------------------------------------------------------------------------
+size_t replica_bytes() { return sizeof(Replica); }
+
+// Workgroups lattice i needs with `rows_pp` domains per pass and P passes.
+uint32_t batch_wgs(const Geom &g, int P) {
+    const uint64_t D = (uint64_t)(g.h == 16 ? 32 : 64) * P;
+    return (uint32_t)((g.K + D - 1) / D);
+}
+
+// Fill the descriptors (host memory) and check the launch fits on the device.
+hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t *ncycles, uint32_t obs_every,
+                      uint32_t n, int P, Replica *out, int &grid, int &block) {
+    if (n == 0) return hipErrorInvalidValue;
+    const int h = gs[0]->h;
+    block = h == 16 ? 512 : 1024;
+    void *kern = select_kernel(h, P, block, true);
+    if (!kern) return hipErrorInvalidValue;
+    uint32_t first = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (gs[i]->h != h) return hipErrorInvalidValue;
+        out[i].g = *gs[i];
+        out[i].G = batch_wgs(*gs[i], P);
+        out[i].xs = scratch_of(*gs[i], (int)out[i].G);
+        out[i].n0 = n0[i];
+        out[i].ncycles = ncycles[i];
+        out[i].obs_every = obs_every;
+        out[i].first_wg = first;
+        out[i].pad = 0;
+        first += out[i].G;
+    }
+    int dev = 0, cus = 0, occ = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, 0);
+    if (e != hipSuccess) return e;
+    if (first > (uint32_t)occ * (uint32_t)cus || first > (uint32_t)kMaxGrid) return hipErrorCooperativeLaunchTooLarge;
+    grid = (int)first;
+    return hipSuccess;
+}
+
+// Descriptors reach device memory as kernel arguments (copied at launch, so the
+// host array may go away at once): up to kUploadPer per launch.
+constexpr uint32_t kUploadPer = 8;
+struct ReplicaPack {
+    Replica r[kUploadPer];
+};
+__global__ void k_upload(ReplicaPack pack, uint32_t count, Replica *dst) {
+    const uint32_t words = (uint32_t)(sizeof(Replica) / sizeof(uint32_t));
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&pack);
+    uint32_t *out = reinterpret_cast<uint32_t *>(dst);
+    for (uint32_t i = threadIdx.x; i < count * words; i += blockDim.x) out[i] = src[i];
+}
+hipError_t upload_replicas(const Replica *host, uint32_t n, Replica *dev, hipStream_t stream) {
+    for (uint32_t i = 0; i < n; i += kUploadPer) {
+        ReplicaPack pack;
+        uint32_t cnt = n - i < kUploadPer ? n - i : kUploadPer;
+        for (uint32_t j = 0; j < cnt; ++j) pack.r[j] = host[i + j];
+        hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, stream, pack, cnt, dev + i);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// The descriptors must already be in device memory (dev_reps).
+hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipStream_t stream) {
+    void *kern = select_kernel(h, P, block, true);
+    if (!kern) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_persistent_prep_batch, dim3(n < 64 ? n : 64), dim3(256), 0, stream, dev_reps, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const Replica *reps = dev_reps;
+    void *args[] = {&reps, &n};
     return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(block), args, 0, stream);
 }
 

@@ -19,6 +19,12 @@ hipError_t persistent_configure(const Geom &g, const spkmc_params &p, int &grid,
 hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid,
                              int block, int wg_domains, hipStream_t stream);
 uint64_t persistent_scratch_words(uint64_t K);
+struct Replica;
+size_t replica_bytes();
+hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t *ncycles, uint32_t obs_every,
+                      uint32_t n, int P, Replica *out, int &grid, int &block);
+hipError_t upload_replicas(const Replica *host, uint32_t n, Replica *dev, hipStream_t stream);
+hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipStream_t stream);
 }  // namespace spkmc
 
 using namespace spkmc;
@@ -459,6 +465,80 @@ spkmc_status spkmc_query(const spkmc_ctx *c, spkmc_info *out) {
     out->state_bytes = c->spin_off + c->spin_bytes;
     double h = c->g.h;
     out->bytes_per_cycle = (double)c->g.K * ((h * h * h + 6.0 * h * h) / 8.0 + 8.0);
+    return SPKMC_OK;
+}
+
+size_t spkmc_batch_workspace_bytes(size_t n) { return align256(n * replica_bytes()); }
+
+spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
+                             int32_t wg_domains, void *dev_workspace, size_t ws_bytes, spkmc_batch_info *info) {
+    if (!ctxs || !ncycles || n == 0) return fail(nullptr, SPKMC_E_INVAL, "no lattices");
+    if (!dev_workspace || ws_bytes < spkmc_batch_workspace_bytes(n))
+        return fail(nullptr, SPKMC_E_RANGE, "batch workspace too small");
+    std::vector<const Geom *> gs;
+    std::vector<uint64_t> n0, nc;
+    std::vector<spkmc_ctx *> live;
+    hipStream_t stream = nullptr;
+    int h = 0;
+    for (size_t i = 0; i < n; ++i) {
+        spkmc_ctx *c = ctxs[i];
+        if (!c) return fail(nullptr, SPKMC_E_INVAL, "NULL context in batch");
+        if (c->failed || !c->dev) return fail(nullptr, SPKMC_E_STATE, "a context of the batch is in a failed state");
+        if (ncycles[i] == 0) continue;
+        std::string why;
+        if (!persistent_supported(c->g, c->p, why)) return fail(nullptr, SPKMC_E_UNSUPPORTED, "batch member: " + why);
+        if (live.empty()) {
+            stream = c->stream;
+            h = c->g.h;
+        } else if (c->stream != stream || c->g.h != h) {
+            return fail(nullptr, SPKMC_E_INVAL, "batch members must share the stream and the octant edge");
+        }
+        live.push_back(c);
+        gs.push_back(&c->g);
+        n0.push_back(c->cycle);
+        nc.push_back(ncycles[i]);
+    }
+    if (live.empty()) return SPKMC_OK;
+    const int rows = h == 16 ? 32 : 64;
+    std::vector<int> Ps;
+    if (wg_domains) {
+        if (wg_domains % rows || (wg_domains / rows != 1 && wg_domains / rows != 2 && wg_domains / rows != 4))
+            return fail(nullptr, SPKMC_E_INVAL, "wg_domains must be 1, 2 or 4 passes of the row count");
+        Ps.push_back(wg_domains / rows);
+    } else {
+        Ps = {1, 2, 4};
+    }
+    std::vector<unsigned char> host(replica_bytes() * live.size());
+    Replica *reps = reinterpret_cast<Replica *>(host.data());
+    int grid = 0, block = 0, P = 0;
+    hipError_t e = hipErrorCooperativeLaunchTooLarge;
+    for (int Pc : Ps) {
+        e = batch_plan(gs.data(), n0.data(), nc.data(), obs_every, (uint32_t)live.size(), Pc, reps, grid, block);
+        if (e == hipSuccess) { P = Pc; break; }
+    }
+    if (e == hipErrorCooperativeLaunchTooLarge)
+        return fail(nullptr, SPKMC_E_UNSUPPORTED, "the batch does not fit on the device at once: split it");
+    if (e != hipSuccess) return fail(nullptr, SPKMC_E_DEVICE, std::string("batch plan: ") + hipGetErrorString(e));
+    e = upload_replicas(reps, (uint32_t)live.size(), reinterpret_cast<Replica *>(dev_workspace), stream);
+    if (e == hipSuccess)
+        e = launch_batch(reinterpret_cast<const Replica *>(dev_workspace), (uint32_t)live.size(), h, P, grid, block, stream);
+    if (e != hipSuccess) {
+        for (spkmc_ctx *c : live) c->failed = true;
+        return fail(nullptr, SPKMC_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+    }
+    uint64_t domains = 0;
+    for (size_t i = 0; i < live.size(); ++i) {
+        live[i]->cycle += nc[i];
+        domains += live[i]->g.K;
+    }
+    if (info) {
+        info->grid = grid;
+        info->block = block;
+        info->wg_domains = (block / 16) * P;
+        info->h = h;
+        info->lattices = live.size();
+        info->domains = domains;
+    }
     return SPKMC_OK;
 }
 

@@ -44,9 +44,15 @@ class Info(C.Structure):
                 ("state_bytes", C.c_uint64), ("bytes_per_cycle", C.c_double)]
 
 
+class BatchInfo(C.Structure):
+    _fields_ = [("grid", C.c_int32), ("block", C.c_int32), ("wg_domains", C.c_int32), ("h", C.c_int32),
+                ("lattices", C.c_uint64), ("domains", C.c_uint64)]
+
+
 EXPORTS = ["spkmc_state_bytes", "spkmc_init", "spkmc_run", "spkmc_observables", "spkmc_records",
            "spkmc_copy_spins", "spkmc_set_spins", "spkmc_rate_table", "spkmc_save", "spkmc_load",
-           "spkmc_query", "spkmc_last_error", "spkmc_destroy"]
+           "spkmc_query", "spkmc_last_error", "spkmc_destroy", "spkmc_batch_workspace_bytes",
+           "spkmc_run_batch"]
 
 
 def _load():
@@ -82,6 +88,11 @@ def _load():
     lib.spkmc_last_error.argtypes = [vp]
     lib.spkmc_destroy.restype = None
     lib.spkmc_destroy.argtypes = [vp]
+    lib.spkmc_batch_workspace_bytes.restype = C.c_size_t
+    lib.spkmc_batch_workspace_bytes.argtypes = [C.c_size_t]
+    lib.spkmc_run_batch.restype = C.c_int
+    lib.spkmc_run_batch.argtypes = [P(vp), C.c_size_t, P(C.c_uint64), C.c_uint32, C.c_int32, vp, C.c_size_t,
+                                    P(BatchInfo)]
     return lib
 
 
@@ -205,3 +216,34 @@ class Sim:
         i = Info()
         self._check(lib.spkmc_query(self.ctx, C.byref(i)))
         return {f: getattr(i, f) for f, _ in Info._fields_}
+
+
+_workspace = {}
+
+
+def run_batch(sims, ncycles, obs_every=0, wg_domains=0):
+    """Run ncycles[i] cycles on each lattice of `sims` (same device, stream and
+    octant edge) in one persistent launch; returns the launch shape."""
+    import torch
+    n = len(sims)
+    if n == 0:
+        return None
+    if isinstance(ncycles, int):
+        ncycles = [ncycles] * n
+    need = lib.spkmc_batch_workspace_bytes(n)
+    dev = sims[0].device
+    # one workspace per stream: launches on one stream run in order, so the next
+    # batch's descriptors never overwrite those of a batch still running
+    key = (str(dev), sims[0].stream.cuda_stream)
+    ws = _workspace.get(key)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1 << 16), dtype=torch.uint8, device=dev)
+        _workspace[key] = ws
+    ctxs = (C.c_void_p * n)(*[sim.ctx.value for sim in sims])
+    cyc = (C.c_uint64 * n)(*[int(c) for c in ncycles])
+    info = BatchInfo()
+    st = lib.spkmc_run_batch(ctxs, n, cyc, int(obs_every), int(wg_domains), C.c_void_p(ws.data_ptr()),
+                             ws.numel(), C.byref(info))
+    if st != OK:
+        raise SpkmcError(st, lib.spkmc_last_error(None).decode())
+    return {f: getattr(info, f) for f, _ in BatchInfo._fields_}

@@ -1,0 +1,94 @@
+"""Batched replicas (many independent lattices in one persistent launch):
+every lattice of a batch ends bit-identical to the same lattice run alone."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spkmc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1005_4713_amd import spkmc as mod
+    return mod
+
+
+def _mix(d, Ls, seed0):
+    rng = np.random.default_rng(seed0)
+    out = []
+    for i, L in enumerate(Ls):
+        out.append(dict(L=L, domain=d, T=float(rng.uniform(4.0, 5.0)), H=float(rng.choice([0.0, 0.05, -0.05])),
+                        seed=seed0 * 100 + i, init=["random", "up", "down"][i % 3],
+                        rates=["glauber", "metropolis"][i % 2]))
+    return out
+
+
+def _sims(spkmc, mix, **kw):
+    return [spkmc.Sim(m["L"], m["domain"], T=m["T"], H=m["H"], seed=m["seed"], init=m["init"], rates=m["rates"],
+                      layout="packed", engine="persistent", record_cap=128, **kw) for m in mix]
+
+
+@pytest.mark.parametrize("d,Ls", [(16, [32, 48, 64, 96, 128, 32, 48]), (32, [64, 128, 256, 64])])
+def test_batch_equals_solo(spkmc, d, Ls):
+    print("case", d, Ls, flush=True)
+    mix = _mix(d, Ls, d)
+    batch = _sims(spkmc, mix)
+    solo = _sims(spkmc, mix)
+    ncyc = [150 + 37 * i for i in range(len(mix))]
+    # three macro-steps of uneven length for the batch, one launch per lattice alone
+    done = [0] * len(mix)
+    for step in (50, 60, 1000):
+        want = [min(step, ncyc[i] - done[i]) for i in range(len(mix))]
+        info = spkmc.run_batch(batch, want, obs_every=10)
+        done = [a + b for a, b in zip(done, want)]
+        assert info is None or info["lattices"] == sum(1 for w in want if w)
+    for s, n in zip(solo, ncyc):
+        s.run(n, obs_every=10)
+    for b, s in zip(batch, solo):
+        assert b.state() == s.state()
+        assert b.records() == s.records()
+        assert np.array_equal(b.spins(), s.spins())
+
+
+def test_batch_member_vs_oracle(spkmc):
+    mix = _mix(16, [48, 64, 32], 7)
+    batch = _sims(spkmc, mix)
+    spkmc.run_batch(batch, [120, 80, 100], obs_every=20)
+    m = mix[0]
+    orc = oracle.Sim(L=m["L"], d=m["domain"], T=m["T"], H=m["H"], seed=m["seed"], init=0, rates=0)
+    ro = orc.run(120, obs_every=20)
+    rg = batch[0].records()
+    assert [r[:3] for r in rg] == [r[:3] for r in ro]
+    assert [r[4:] for r in rg] == [r[4:] for r in ro]
+    for g_, o_ in zip(rg, ro):
+        assert abs(g_[3] - o_[3]) <= 1e-12 * o_[3]
+    assert np.array_equal(batch[0].spins(), orc.spins())
+
+
+def test_batch_launch_shapes_identical(spkmc):
+    mix = _mix(16, [64, 128, 96], 11)
+    ref = None
+    for wd in (64, 128, 256):
+        sims = _sims(spkmc, mix)
+        info = spkmc.run_batch(sims, 90, obs_every=9, wg_domains=wd)
+        assert info["wg_domains"] == wd
+        out = [(s.state(), s.records(), s.spins().tobytes()) for s in sims]
+        if ref is None:
+            ref = out
+        else:
+            assert out == ref
+
+
+def test_batch_rejects_mixed_edges(spkmc):
+    a = spkmc.Sim(64, 16, layout="packed", seed=1)
+    b = spkmc.Sim(64, 32, layout="packed", seed=2)
+    with pytest.raises(spkmc.SpkmcError):
+        spkmc.run_batch([a, b], 10)
+    # the contexts are still usable
+    a.run(5)
+    b.run(5)
+    assert a.state()[0] == 5 and b.state()[0] == 5
