@@ -30,7 +30,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500, help="timed cycles")
     ap.add_argument("--warmup", type=int, default=50, help="untimed cycles before the timed region")
-    ap.add_argument("--workload", default="headline", choices=["headline", "l512", "l128"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "l512", "l128", "batch", "serve"])
+    ap.add_argument("--replicas", type=int, default=256, help="batch / serve: lattices in the replica mix")
+    ap.add_argument("--cycles", type=int, default=1000, help="batch / serve: cycles per lattice")
     ap.add_argument("--engine", default="auto", choices=["auto", "cycle", "persistent"])
     ap.add_argument("--wg-domains", type=int, default=0)
     ap.add_argument("--obs-every", type=int, default=10)
@@ -106,6 +108,55 @@ def cpu_baseline(w, cycles):
             "attempts_per_s": (st1[1] + st1[2] - st0[1] - st0[2]) / dt}
 
 
+def bench_serve(args):
+    raise SystemExit("serving benchmark not built yet")
+
+
+def bench_batch(args):
+    """The replica mix (L in {32..256}, T in [4, 5], H in {0, +-0.05}, 1000 cycles
+    each) run as tuned batched launches, against the plain single-lattice path
+    (every lattice alone, one launch per lattice, one after another)."""
+    import torch
+    from paper_1005_4713_amd import spkmc, tune, workloads
+    specs = workloads.replica_mix(args.replicas)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    plan, table = tune.tune(specs, probe_cycles=20, log=log)
+    sims = tune.build(specs, plan["domains"])
+    torch.cuda.synchronize()
+    s0 = [s.state() for s in sims]
+    t0 = time.perf_counter()
+    tune.run_plan(plan, sims, args.cycles)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s1 = [s.state() for s in sims]
+    fired = sum(b[1] - a[1] for a, b in zip(s0, s1))
+    attempts = sum(b[1] + b[2] - a[1] - a[2] for a, b in zip(s0, s1))
+    del sims
+    # plain path: the same lattices, one at a time
+    solo = tune.build(specs, plan["domains"])
+    torch.cuda.synchronize()
+    q0 = [s.state() for s in solo]
+    t1 = time.perf_counter()
+    for s in solo:
+        s.run(args.cycles)
+    torch.cuda.synchronize()
+    dt_solo = time.perf_counter() - t1
+    q1 = [s.state() for s in solo]
+    fired_solo = sum(b[1] - a[1] for a, b in zip(q0, q1))
+    same = all(a == b for a, b in zip(s1, q1))
+    out = {"metric": "spin-flip events/s, batched replica mix", "value": fired / dt, "unit": "spin-flip events/s",
+           "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "u32+f64",
+           "config": {"workload": f"replica_mix_{args.replicas}", "cycles": args.cycles,
+                      "domains_policy": plan["policy"], "passes": plan["passes"],
+                      "launches": len(plan["launches"]),
+                      "sites": sum(sp["L"] ** 3 for sp in specs)},
+           "seconds": dt, "attempts_per_s": attempts / dt,
+           "plain": {"value": fired_solo / dt_solo, "seconds": dt_solo, "kind": "each lattice alone, in turn"},
+           "speedup_vs_plain": (fired / dt) / (fired_solo / dt_solo), "bit_identical_to_plain": same,
+           "tuner": table}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -118,6 +169,14 @@ def main():
         return
     from paper_1005_4713_amd import spkmc
 
+    if args.workload == "batch":
+        torch.cuda.set_device(0)
+        bench_batch(args)
+        return
+    if args.workload == "serve":
+        torch.cuda.set_device(0)
+        bench_serve(args)
+        return
     w = workload(args.workload)
     torch.cuda.set_device(0)
     print(f"bench: workload {w['name']} engine={args.engine} warmup={args.warmup} steps={args.steps}",
