@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -33,6 +35,7 @@ def parse():
     ap.add_argument("--workload", default="headline", choices=["headline", "l512", "l128", "batch", "serve"])
     ap.add_argument("--replicas", type=int, default=256, help="batch / serve: lattices in the replica mix")
     ap.add_argument("--cycles", type=int, default=1000, help="batch / serve: cycles per lattice")
+    ap.add_argument("--macro-cycles", type=int, default=100, help="serve: cycles per macro-step")
     ap.add_argument("--engine", default="auto", choices=["auto", "cycle", "persistent"])
     ap.add_argument("--wg-domains", type=int, default=0)
     ap.add_argument("--obs-every", type=int, default=10)
@@ -108,8 +111,94 @@ def cpu_baseline(w, cycles):
             "attempts_per_s": (st1[1] + st1[2] - st0[1] - st0[2]) / dt}
 
 
+def _serve_run(spkmc, specs, doms, arrivals, pool_bytes, macro, max_live, log):
+    """Submit request i at arrivals[i] seconds (real time) and step the server
+    until every request is done; returns per-request latencies and totals."""
+    srv = spkmc.Server(pool_bytes, macro_cycles=macro, max_live=max_live, inflight=2)
+    n = len(specs)
+    ids = [None] * n
+    t0 = srv.clock()
+    i = 0
+    steps = 0
+    while True:
+        now = srv.clock() - t0
+        while i < n and arrivals[i] <= now:
+            sp = specs[i]
+            ids[i] = srv.submit(sp["L"], doms[i], sp["cycles"], T=sp["T"], H=sp["H"], seed=sp["seed"],
+                                t_arrival=t0 + arrivals[i], record_cap=0)
+            i += 1
+        st = srv.step(wait=False)
+        steps += 1
+        busy = st["queued"] or st["live"] or st["inflight"]
+        if i == n and not busy:
+            break
+        if not busy and i < n:
+            gap = arrivals[i] - (srv.clock() - t0)
+            if gap > 2e-4:
+                time.sleep(gap - 1e-4)
+    res = [srv.poll(r) for r in ids]
+    srv.close()
+    lat = np.array([r["t_done"] - r["t_arrival"] for r in res])
+    wait = np.array([r["t_admit"] - r["t_arrival"] for r in res])
+    fired = sum(r["state_tuple"][1] for r in res)
+    attempts = sum(r["state_tuple"][1] + r["state_tuple"][2] for r in res)
+    span = max(r["t_done"] for r in res) - (t0 + float(arrivals[0]))
+    out = {"requests": n, "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "mean_ms": float(lat.mean() * 1e3), "max_ms": float(lat.max() * 1e3),
+           "admission_wait_p99_ms": float(np.percentile(wait, 99) * 1e3),
+           "makespan_s": span, "events_per_s": fired / span, "attempts_per_s": attempts / span,
+           "pool_bytes": pool_bytes, "pool_peak": st["pool_peak"], "macro_cycles": macro,
+           "macro_steps": st["macro_steps"], "launches": st["launches"], "host_steps": steps}
+    log(f"serve: {n} requests, p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms, "
+        f"makespan {span:.3f} s, pool peak {st['pool_peak'] / 2**20:.1f} MiB")
+    return out, [r["state_tuple"] for r in res]
+
+
 def bench_serve(args):
-    raise SystemExit("serving benchmark not built yet")
+    """The replica mix served as requests: Poisson arrivals at 50/s (seed 6)
+    into the request server with the admission cap at 200 GB (the whole mix
+    needs far less, so it never binds: the pool is the mix's total footprint);
+    the same mix arriving at once; and at once under a 16 MiB cap, which makes
+    admission wait for memory.  Latency = completion seen by the host minus
+    arrival.  Every served result is checked against the plain path."""
+    import torch
+    from paper_1005_4713_amd import spkmc, tune, workloads
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    specs = workloads.replica_mix(args.replicas)
+    for sp in specs:
+        sp["cycles"] = args.cycles
+    plan, _ = tune.tune(specs, probe_cycles=20, log=log)
+    doms = plan["domains"]
+    foot = sum((spkmc.state_bytes(spkmc.make_params(sp["L"], d)) + 255) // 256 * 256 for sp, d in zip(specs, doms))
+    cap = int(200e9)
+    arr = workloads.arrivals(len(specs), rate=50.0, seed=6)
+    # plain path: each lattice alone, in turn
+    solo = tune.build(specs, doms)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in solo:
+        s.run(args.cycles)
+    torch.cuda.synchronize()
+    dt_solo = time.perf_counter() - t1
+    plain_states = [s.state() for s in solo]
+    del solo
+    fired_plain = sum(s[1] for s in plain_states)
+    macro = args.macro_cycles
+    poisson, st_p = _serve_run(spkmc, specs, doms, arr, min(cap, foot), macro, 512, log)
+    burst, st_b = _serve_run(spkmc, specs, doms, np.zeros(len(specs)), min(cap, foot), macro, 512, log)
+    capped, st_c = _serve_run(spkmc, specs, doms, np.zeros(len(specs)), 16 << 20, macro, 512, log)
+    same = st_p == plain_states and st_b == plain_states and st_c == plain_states
+    out = {"metric": "served replica mix: p50/p99 latency", "value": poisson["p99_ms"], "unit": "ms (p99)",
+           "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "u32+f64",
+           "config": {"workload": f"replica_mix_{args.replicas}_served", "cycles": args.cycles,
+                      "arrivals": "Poisson 50/s, seed 6", "admission_cap_bytes": cap, "mix_footprint_bytes": foot,
+                      "domains_policy": plan["policy"]},
+           "p50_ms": poisson["p50_ms"], "p99_ms": poisson["p99_ms"],
+           "poisson_50_per_s": poisson, "burst": burst, "burst_cap_16MiB": capped,
+           "plain": {"events_per_s": fired_plain / dt_solo, "seconds": dt_solo, "kind": "each lattice alone, in turn"},
+           "burst_vs_plain": burst["events_per_s"] / (fired_plain / dt_solo),
+           "bit_identical_to_plain": same}
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args):

@@ -209,6 +209,123 @@ size_t spkmc_batch_workspace_bytes(size_t n);
 spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
                              int32_t wg_domains, void *dev_workspace, size_t ws_bytes, spkmc_batch_info *info);
 
+/* ------------------------------------------------------------------------- */
+/* Serving: a request loop with continuous batching.                          */
+/* ------------------------------------------------------------------------- */
+/* A server owns a caller-provided device pool and a stream.  Requests (one
+ * lattice each: spkmc_params, a cycle count and an observation interval) are
+ * queued in FIFO order and admitted while a slot is free and their footprint
+ * (spkmc_state_bytes, first fit in the pool) fits; the lattice and its clock
+ * then stay resident in the pool until the request has run all its cycles.
+ * All resident requests advance together in macro-steps of macro_cycles
+ * cycles: per macro-step, PACKED lattices with an octant edge of 8 or 16 share
+ * cooperative batch launches (one per edge, split only where the device cannot
+ * hold them at once); the others run alone with spkmc_run.  Requests that
+ * arrive while others run join at the next macro-step.  A macro-step is only
+ * a scheduling unit: the random streams are keyed by each lattice's own cycle
+ * number, so every request ends bit-identical to running it alone with
+ * spkmc_init + spkmc_run (engine, wg_domains and the launch shape never change
+ * results).  Times are seconds on the server's monotonic clock (0 = creation).
+ *
+ * Threading: a server and its requests are driven from one thread at a time.
+ * The pool, the stream and the server's pinned host slots are used until
+ * spkmc_server_destroy returns. */
+typedef struct spkmc_server spkmc_server;
+
+typedef struct spkmc_server_config {
+    uint32_t struct_size;   /* sizeof(spkmc_server_config)                        */
+    uint32_t macro_cycles;  /* cycles per macro-step, > 0                         */
+    uint32_t max_live;      /* requests resident at once, 1..4096                 */
+    uint32_t inflight;      /* macro-steps enqueued ahead of the device, 1..8     */
+    int32_t wg_domains;     /* batch launches: domains per workgroup (0 = fewest
+                               passes that fit); never changes results            */
+    uint32_t reserved;      /* must be 0                                          */
+} spkmc_server_config;
+
+enum {
+    SPKMC_REQ_QUEUED = 0,   /* waiting for a slot and pool memory                   */
+    SPKMC_REQ_RUNNING = 1,  /* resident; macro-steps enqueued                       */
+    SPKMC_REQ_DONE = 2,     /* all cycles finished on the device; obs valid         */
+    SPKMC_REQ_FAILED = 3    /* rejected at admission or a launch failed (message in
+                               spkmc_server_last_error at the time)                 */
+};
+
+/* submit flags */
+enum { SPKMC_SERVE_KEEP = 1 }; /* keep the lattice resident after DONE, so that
+                                  spkmc_server_context can be used to read spins
+                                  and records, until spkmc_server_release      */
+
+typedef struct spkmc_request_status {
+    int32_t state;          /* SPKMC_REQ_*                                         */
+    uint32_t flags;         /* as submitted                                        */
+    uint64_t ncycles;       /* cycles requested                                    */
+    uint64_t cycles_enqueued;
+    uint64_t bytes;         /* pool footprint                                      */
+    double t_arrival;       /* as submitted (or the submit time)                   */
+    double t_admit;         /* admission (-1 while queued)                         */
+    double t_done;          /* first time step() saw the last macro-step finished  */
+    spkmc_obs obs;          /* final state when DONE                               */
+} spkmc_request_status;
+
+typedef struct spkmc_server_stats {
+    uint64_t queued, live, finishing, done, failed; /* requests by state; finishing =
+                                                       last macro-step enqueued, not
+                                                       yet seen finished            */
+    uint64_t macro_steps;     /* macro-steps enqueued                               */
+    uint64_t launches;        /* batch launches + solo runs enqueued                */
+    uint64_t pool_in_use;     /* bytes of the pool held by resident requests        */
+    uint64_t pool_peak;       /* high-water mark of pool_in_use                     */
+    uint64_t inflight;        /* macro-steps enqueued and not yet seen finished     */
+} spkmc_server_stats;
+
+/* Bytes of the pool the server reserves for itself (batch descriptors) for this
+ * configuration; 0 if the configuration is invalid.  The rest holds lattices. */
+size_t spkmc_server_reserved_bytes(const spkmc_server_config *cfg);
+
+/* Create a server over dev_pool (pool_bytes of device memory owned by the
+ * caller; 256-byte aligned) and hip_stream (a hipStream_t; NULL = null stream).
+ * Allocates host memory and max_live * (inflight + 1) pinned 256-byte slots.
+ * Errors: E_INVAL (bad configuration or pool), E_RANGE (pool smaller than the
+ * reserved bytes), E_NOMEM, E_DEVICE. */
+spkmc_status spkmc_server_create(const spkmc_server_config *cfg, void *dev_pool, size_t pool_bytes,
+                                 void *hip_stream, spkmc_server **out);
+
+/* Queue a request; *id receives its id (ids start at 1 and are never reused).
+ * t_arrival < 0 means now.  obs_every as in spkmc_run.  The parameters are
+ * validated at once (E_INVAL as spkmc_init; E_RANGE if the footprint exceeds
+ * what the pool can ever hold). */
+spkmc_status spkmc_server_submit(spkmc_server *s, const spkmc_params *p, uint64_t ncycles, uint32_t obs_every,
+                                 uint32_t flags, double t_arrival, uint64_t *id);
+
+/* Make progress without blocking the device: retire macro-steps the device has
+ * finished (their finishing requests become DONE), admit queued requests, and
+ * enqueue macro-steps until `inflight` are outstanding.  With wait != 0 and
+ * nothing retired, first block until the oldest outstanding macro-step has
+ * finished.  stats (may be NULL) receives the counts after the call. */
+spkmc_status spkmc_server_step(spkmc_server *s, int wait, spkmc_server_stats *stats);
+
+/* Status of a request (E_INVAL for an unknown or released id). */
+spkmc_status spkmc_server_poll(const spkmc_server *s, uint64_t id, spkmc_request_status *out);
+
+/* The context of a DONE request submitted with SPKMC_SERVE_KEEP, for
+ * spkmc_copy_spins / spkmc_records / spkmc_observables / spkmc_save.  It stays
+ * owned by the server and is valid until spkmc_server_release. */
+spkmc_status spkmc_server_context(spkmc_server *s, uint64_t id, spkmc_ctx **ctx);
+
+/* Forget a DONE or FAILED request and free what it still holds (the lattice
+ * of a kept request).  E_STATE while it is queued or running. */
+spkmc_status spkmc_server_release(spkmc_server *s, uint64_t id);
+
+/* Seconds since the server was created (its clock). */
+double spkmc_server_clock(const spkmc_server *s);
+
+/* Message of the last failure of a call on s (s == NULL: as spkmc_last_error(NULL)). */
+const char *spkmc_server_last_error(const spkmc_server *s);
+
+/* Synchronise the stream, then free the server, its contexts and pinned slots
+ * (not the pool or the stream). */
+void spkmc_server_destroy(spkmc_server *s);
+
 /* Message of the last failure on ctx (ctx == NULL: of the last failed call
  * that had no context on this thread).  Never NULL. */
 const char *spkmc_last_error(const spkmc_ctx *ctx);

@@ -1,0 +1,50 @@
+// api_internal.hpp -- host-side pieces shared by the C ABI and the request server.
+#pragma once
+
+#include <string>
+
+#include "spkmc_device.hpp"
+
+namespace spkmc {
+hipError_t launch_init(const Geom &g, int init, hipStream_t stream);
+hipError_t launch_faces(const Geom &g, hipStream_t stream);
+hipError_t launch_observables(const Geom &g, hipStream_t stream);
+hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream_t stream);
+bool persistent_supported(const Geom &g, const spkmc_params &p, std::string &why);
+hipError_t persistent_configure(const Geom &g, const spkmc_params &p, int &grid, int &block, int &wg_domains);
+hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid,
+                             int block, int wg_domains, hipStream_t stream);
+uint64_t persistent_scratch_words(uint64_t K);
+struct Replica;
+size_t replica_bytes();
+hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t *ncycles, uint32_t obs_every,
+                      uint32_t n, int P, Replica *out, int &grid, int &block);
+hipError_t upload_replicas(const Replica *host, uint32_t n, Replica *dev, hipStream_t stream);
+hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipStream_t stream);
+}  // namespace spkmc
+
+struct spkmc_ctx {
+    spkmc_params p;
+    hipStream_t stream;
+    char *dev;
+    size_t dev_bytes;
+    spkmc::Geom g;
+    size_t spin_off, spin_bytes;   // spin region (A + F, or int8), for save/load
+    size_t rec_off;
+    uint64_t cycle;                // cycles enqueued
+    int engine;
+    int grid, block, wg_domains;
+    bool failed;
+    std::string err;
+};
+
+namespace spkmc {
+// Workgroups the batch kernel for octant edge h with P passes can keep resident
+// at once on the current device (0 on error).
+uint32_t batch_capacity(int h, int P);
+uint32_t batch_wgs(const Geom &g, int P);
+
+// The observables of a lattice of N sites with parameters p from a copy of its
+// device state header.
+void obs_from_state(const spkmc_params &p, uint64_t N, const DevState &st, spkmc_obs *out);
+}  // namespace spkmc

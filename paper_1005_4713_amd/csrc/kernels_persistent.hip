@@ -963,6 +963,20 @@ uint32_t batch_wgs(const Geom &g, int P) {
     return (uint32_t)((g.K + D - 1) / D);
 }
 
+// Workgroups of the batch kernel for octant edge h and P passes that the
+// current device keeps resident at once (0 on error).
+uint32_t batch_capacity(int h, int P) {
+    const int block = h == 16 ? 512 : 1024;
+    void *kern = select_kernel(h, P, block, true);
+    if (!kern) return 0;
+    int dev = 0, cus = 0, occ = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, 0) != hipSuccess) return 0;
+    uint64_t cap = (uint64_t)occ * (uint64_t)cus;
+    return (uint32_t)(cap < kMaxGrid ? cap : kMaxGrid);
+}
+
 // Fill the descriptors (host memory) and check the launch fits on the device.
 hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t *ncycles, uint32_t obs_every,
                       uint32_t n, int P, Replica *out, int &grid, int &block) {
@@ -984,12 +998,9 @@ hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t 
         out[i].pad = 0;
         first += out[i].G;
     }
-    int dev = 0, cus = 0, occ = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, 0);
-    if (e != hipSuccess) return e;
-    if (first > (uint32_t)occ * (uint32_t)cus || first > (uint32_t)kMaxGrid) return hipErrorCooperativeLaunchTooLarge;
+    const uint32_t cap = batch_capacity(h, P);
+    if (cap == 0) return hipErrorInvalidValue;
+    if (first > cap) return hipErrorCooperativeLaunchTooLarge;
     grid = (int)first;
     return hipSuccess;
 }

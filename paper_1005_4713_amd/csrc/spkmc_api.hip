@@ -7,42 +7,9 @@
 #include <string>
 #include <vector>
 
-#include "spkmc_device.hpp"
-
-namespace spkmc {
-hipError_t launch_init(const Geom &g, int init, hipStream_t stream);
-hipError_t launch_faces(const Geom &g, hipStream_t stream);
-hipError_t launch_observables(const Geom &g, hipStream_t stream);
-hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream_t stream);
-bool persistent_supported(const Geom &g, const spkmc_params &p, std::string &why);
-hipError_t persistent_configure(const Geom &g, const spkmc_params &p, int &grid, int &block, int &wg_domains);
-hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid,
-                             int block, int wg_domains, hipStream_t stream);
-uint64_t persistent_scratch_words(uint64_t K);
-struct Replica;
-size_t replica_bytes();
-hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t *ncycles, uint32_t obs_every,
-                      uint32_t n, int P, Replica *out, int &grid, int &block);
-hipError_t upload_replicas(const Replica *host, uint32_t n, Replica *dev, hipStream_t stream);
-hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipStream_t stream);
-}  // namespace spkmc
+#include "api_internal.hpp"
 
 using namespace spkmc;
-
-struct spkmc_ctx {
-    spkmc_params p;
-    hipStream_t stream;
-    char *dev;
-    size_t dev_bytes;
-    Geom g;
-    size_t spin_off, spin_bytes;   // spin region (A + F, or int8), for save/load
-    size_t rec_off;
-    uint64_t cycle;                // cycles enqueued
-    int engine;
-    int grid, block, wg_domains;
-    bool failed;
-    std::string err;
-};
 
 static thread_local std::string g_last_error = "no error";
 
@@ -134,6 +101,19 @@ static LayoutPlan plan(const spkmc_params *p) {
     return lp;
 }
 
+void spkmc::obs_from_state(const spkmc_params &p, uint64_t N, const DevState &st, spkmc_obs *out) {
+    out->rec.cycle = st.cycle;
+    out->rec.fired = st.fired;
+    out->rec.nulls = st.nulls;
+    out->rec.t = st.t;
+    out->rec.M = st.M;
+    out->rec.B = st.B;
+    out->E = -p.J * (double)st.B - p.H * (double)st.M;  // eq. 1
+    out->m = (double)st.M / (double)N;                    // eq. 4
+    uint64_t tot = st.fired + st.nulls;
+    out->ur = tot ? (double)st.fired / (double)tot : 0.0;
+}
+
 #pragma GCC visibility push(default)
 extern "C" {
 
@@ -218,7 +198,17 @@ spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, 
     c->wg_domains = 0;
     if (c->engine == SPKMC_ENGINE_PERSISTENT) {
         hipError_t e = persistent_configure(g, *p, c->grid, c->block, c->wg_domains);
-        if (e != hipSuccess) return hip_fail(c, e, "persistent_configure");
+        if (e == hipErrorCooperativeLaunchTooLarge && p->engine == SPKMC_ENGINE_AUTO) {
+            // more domains than one resident launch holds: the per-cycle engine
+            c->engine = SPKMC_ENGINE_CYCLE;
+            c->grid = (int)g.K;
+            c->block = 256;
+            c->wg_domains = 0;
+        } else if (e == hipErrorCooperativeLaunchTooLarge) {
+            return fail(c, SPKMC_E_UNSUPPORTED, "persistent engine: the domains do not fit in one resident launch");
+        } else if (e != hipSuccess) {
+            return hip_fail(c, e, "persistent_configure");
+        }
     }
 
     hipError_t e;
@@ -269,16 +259,7 @@ spkmc_status spkmc_observables(spkmc_ctx *c, spkmc_obs *out) {
     DevState st;
     spkmc_status s = read_state(c, st);
     if (s != SPKMC_OK) return s;
-    out->rec.cycle = st.cycle;
-    out->rec.fired = st.fired;
-    out->rec.nulls = st.nulls;
-    out->rec.t = st.t;
-    out->rec.M = st.M;
-    out->rec.B = st.B;
-    out->E = -c->p.J * (double)st.B - c->p.H * (double)st.M;
-    out->m = (double)st.M / (double)c->g.N;
-    uint64_t tot = st.fired + st.nulls;
-    out->ur = tot ? (double)st.fired / (double)tot : 0.0;
+    obs_from_state(c->p, c->g.N, st, out);
     return SPKMC_OK;
 }
 

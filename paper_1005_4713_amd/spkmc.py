@@ -49,10 +49,32 @@ class BatchInfo(C.Structure):
                 ("lattices", C.c_uint64), ("domains", C.c_uint64)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("macro_cycles", C.c_uint32), ("max_live", C.c_uint32),
+                ("inflight", C.c_uint32), ("wg_domains", C.c_int32), ("reserved", C.c_uint32)]
+
+
+class RequestStatus(C.Structure):
+    _fields_ = [("state", C.c_int32), ("flags", C.c_uint32), ("ncycles", C.c_uint64),
+                ("cycles_enqueued", C.c_uint64), ("bytes", C.c_uint64), ("t_arrival", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("obs", Obs)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("queued", C.c_uint64), ("live", C.c_uint64), ("finishing", C.c_uint64), ("done", C.c_uint64),
+                ("failed", C.c_uint64), ("macro_steps", C.c_uint64), ("launches", C.c_uint64),
+                ("pool_in_use", C.c_uint64), ("pool_peak", C.c_uint64), ("inflight", C.c_uint64)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = range(4)
+SERVE_KEEP = 1
+
 EXPORTS = ["spkmc_state_bytes", "spkmc_init", "spkmc_run", "spkmc_observables", "spkmc_records",
            "spkmc_copy_spins", "spkmc_set_spins", "spkmc_rate_table", "spkmc_save", "spkmc_load",
            "spkmc_query", "spkmc_last_error", "spkmc_destroy", "spkmc_batch_workspace_bytes",
-           "spkmc_run_batch"]
+           "spkmc_run_batch", "spkmc_server_reserved_bytes", "spkmc_server_create", "spkmc_server_submit",
+           "spkmc_server_step", "spkmc_server_poll", "spkmc_server_context", "spkmc_server_release",
+           "spkmc_server_clock", "spkmc_server_last_error", "spkmc_server_destroy"]
 
 
 def _load():
@@ -93,6 +115,27 @@ def _load():
     lib.spkmc_run_batch.restype = C.c_int
     lib.spkmc_run_batch.argtypes = [P(vp), C.c_size_t, P(C.c_uint64), C.c_uint32, C.c_int32, vp, C.c_size_t,
                                     P(BatchInfo)]
+    lib.spkmc_server_reserved_bytes.restype = C.c_size_t
+    lib.spkmc_server_reserved_bytes.argtypes = [P(ServerConfig)]
+    lib.spkmc_server_create.restype = C.c_int
+    lib.spkmc_server_create.argtypes = [P(ServerConfig), vp, C.c_size_t, vp, P(vp)]
+    lib.spkmc_server_submit.restype = C.c_int
+    lib.spkmc_server_submit.argtypes = [vp, P(Params), C.c_uint64, C.c_uint32, C.c_uint32, C.c_double,
+                                        P(C.c_uint64)]
+    lib.spkmc_server_step.restype = C.c_int
+    lib.spkmc_server_step.argtypes = [vp, C.c_int, P(ServerStats)]
+    lib.spkmc_server_poll.restype = C.c_int
+    lib.spkmc_server_poll.argtypes = [vp, C.c_uint64, P(RequestStatus)]
+    lib.spkmc_server_context.restype = C.c_int
+    lib.spkmc_server_context.argtypes = [vp, C.c_uint64, P(vp)]
+    lib.spkmc_server_release.restype = C.c_int
+    lib.spkmc_server_release.argtypes = [vp, C.c_uint64]
+    lib.spkmc_server_clock.restype = C.c_double
+    lib.spkmc_server_clock.argtypes = [vp]
+    lib.spkmc_server_last_error.restype = C.c_char_p
+    lib.spkmc_server_last_error.argtypes = [vp]
+    lib.spkmc_server_destroy.restype = None
+    lib.spkmc_server_destroy.argtypes = [vp]
     return lib
 
 
@@ -134,38 +177,8 @@ def rate_table(params):
     return np.array(list(out))
 
 
-class Sim:
-    """One lattice on one GPU: the device buffer is a torch uint8 tensor, the
-    work runs on torch's current stream of ``device``."""
-
-    def __init__(self, L, domain, device=None, **kw):
-        import torch
-        self.params = make_params(L, domain, **kw)
-        nbytes = state_bytes(self.params)
-        if nbytes == 0:
-            raise SpkmcError(E_INVAL, lib.spkmc_last_error(None).decode())
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        # 256-byte alignment: the caching allocator returns 512-byte aligned blocks
-        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.stream = torch.cuda.current_stream(self.device)
-        self.ctx = C.c_void_p()
-        with torch.cuda.device(self.device):
-            st = lib.spkmc_init(C.byref(self.params), C.c_void_p(self.buf.data_ptr()), nbytes,
-                                C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx))
-        if st != OK:
-            msg = lib.spkmc_last_error(self.ctx if self.ctx else None).decode()
-            self._free()
-            raise SpkmcError(st, msg)
-        self.L = int(L)
-        self.N = self.L ** 3
-
-    def _free(self):
-        if getattr(self, "ctx", None) and self.ctx.value:
-            lib.spkmc_destroy(self.ctx)
-            self.ctx = C.c_void_p()
-
-    def __del__(self):
-        self._free()
+class _Lattice:
+    """Calls on one context (self.ctx, self.params, self.N)."""
 
     def _check(self, st):
         if st != OK:
@@ -218,6 +231,40 @@ class Sim:
         return {f: getattr(i, f) for f, _ in Info._fields_}
 
 
+class Sim(_Lattice):
+    """One lattice on one GPU: the device buffer is a torch uint8 tensor, the
+    work runs on torch's current stream of ``device``."""
+
+    def __init__(self, L, domain, device=None, **kw):
+        import torch
+        self.params = make_params(L, domain, **kw)
+        nbytes = state_bytes(self.params)
+        if nbytes == 0:
+            raise SpkmcError(E_INVAL, lib.spkmc_last_error(None).decode())
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        # 256-byte alignment: the caching allocator returns 512-byte aligned blocks
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.spkmc_init(C.byref(self.params), C.c_void_p(self.buf.data_ptr()), nbytes,
+                                C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx))
+        if st != OK:
+            msg = lib.spkmc_last_error(self.ctx if self.ctx else None).decode()
+            self._free()
+            raise SpkmcError(st, msg)
+        self.L = int(L)
+        self.N = self.L ** 3
+
+    def _free(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            lib.spkmc_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        self._free()
+
+
 _workspace = {}
 
 
@@ -247,3 +294,82 @@ def run_batch(sims, ncycles, obs_every=0, wg_domains=0):
     if st != OK:
         raise SpkmcError(st, lib.spkmc_last_error(None).decode())
     return {f: getattr(info, f) for f, _ in BatchInfo._fields_}
+
+
+class Server:
+    """The request server of the library over a torch device pool and torch's
+    current stream: continuous batching of whole lattices (see spkmc_server_*)."""
+
+    def __init__(self, pool_bytes, macro_cycles=100, max_live=512, inflight=2, wg_domains=0, device=None):
+        import torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        cfg = ServerConfig()
+        cfg.struct_size = C.sizeof(ServerConfig)
+        cfg.macro_cycles, cfg.max_live, cfg.inflight = int(macro_cycles), int(max_live), int(inflight)
+        cfg.wg_domains, cfg.reserved = int(wg_domains), 0
+        self.cfg = cfg
+        self.reserved = lib.spkmc_server_reserved_bytes(C.byref(cfg))
+        if self.reserved == 0:
+            raise SpkmcError(E_INVAL, "invalid server configuration")
+        self.pool = torch.empty(int(pool_bytes) + self.reserved, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.spkmc_server_create(C.byref(cfg), C.c_void_p(self.pool.data_ptr()), self.pool.numel(),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(self.h))
+        if st != OK:
+            raise SpkmcError(st, lib.spkmc_server_last_error(None).decode())
+
+    def _check(self, st):
+        if st != OK:
+            raise SpkmcError(st, lib.spkmc_server_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            lib.spkmc_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        self.close()
+
+    def submit(self, L, domain, ncycles, obs_every=0, keep=False, t_arrival=-1.0, **kw):
+        p = make_params(L, domain, **kw)
+        rid = C.c_uint64()
+        self._check(lib.spkmc_server_submit(self.h, C.byref(p), int(ncycles), int(obs_every),
+                                            SERVE_KEEP if keep else 0, float(t_arrival), C.byref(rid)))
+        return rid.value
+
+    def step(self, wait=False):
+        s = ServerStats()
+        self._check(lib.spkmc_server_step(self.h, 1 if wait else 0, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def poll(self, rid):
+        r = RequestStatus()
+        self._check(lib.spkmc_server_poll(self.h, int(rid), C.byref(r)))
+        out = {f: getattr(r, f) for f, _ in RequestStatus._fields_ if f != "obs"}
+        out["state_tuple"] = r.obs.rec.as_tuple()
+        out["E"], out["m"], out["ur"] = r.obs.E, r.obs.m, r.obs.ur
+        return out
+
+    def lattice(self, rid, L, record_cap=1024):
+        """The kept lattice of a DONE request (valid until release)."""
+        ctx = C.c_void_p()
+        self._check(lib.spkmc_server_context(self.h, int(rid), C.byref(ctx)))
+        v = _Lattice()
+        v.ctx, v.N = ctx, int(L) ** 3
+        v.params = make_params(L, 2, record_cap=record_cap)
+        return v
+
+    def release(self, rid):
+        self._check(lib.spkmc_server_release(self.h, int(rid)))
+
+    def clock(self):
+        return lib.spkmc_server_clock(self.h)
+
+    def drain(self, wait=True):
+        """Step until nothing is queued, resident or in flight."""
+        while True:
+            st = self.step(wait=wait)
+            if st["queued"] == 0 and st["live"] == 0 and st["inflight"] == 0:
+                return st

@@ -98,3 +98,83 @@ def test_state_bytes_scale(spkmc):
     K = 32 ** 3
     assert nb >= 1024 ** 3 // 8 + K * 8 * 6 * 16 * 16 // 8
     assert nb < 1024 ** 3 // 8 * 1.5
+
+
+def _c_layout(spkmc, tmp_path):
+    """sizeof and offsetof of every field of the header's structs, from gcc."""
+    structs = {"spkmc_params": spkmc.Params, "spkmc_record": spkmc.Record, "spkmc_obs": spkmc.Obs,
+               "spkmc_info": spkmc.Info, "spkmc_batch_info": spkmc.BatchInfo,
+               "spkmc_server_config": spkmc.ServerConfig, "spkmc_request_status": spkmc.RequestStatus,
+               "spkmc_server_stats": spkmc.ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "spkmc.h"', "int main(void) {"]
+    for cname, ct in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in ct._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for ln in out.splitlines():
+        a, b, c = ln.split()
+        got[(a, b)] = int(c)
+    return structs, got
+
+
+def test_ctypes_mirrors_match_c_layout(spkmc, tmp_path):
+    # the header compiles as C99 and every ctypes mirror has the same layout
+    structs, got = _c_layout(spkmc, tmp_path)
+    for cname, ct in structs.items():
+        assert got[(cname, "size")] == C.sizeof(ct), cname
+        for f, _ in ct._fields_:
+            assert got[(cname, f)] == getattr(ct, f).offset, (cname, f)
+
+
+def _server_cfg(spkmc, **kw):
+    c = spkmc.ServerConfig()
+    c.struct_size = C.sizeof(spkmc.ServerConfig)
+    c.macro_cycles, c.max_live, c.inflight, c.wg_domains, c.reserved = 100, 16, 2, 0, 0
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("kw", [dict(struct_size=20), dict(macro_cycles=0), dict(max_live=0), dict(max_live=5000),
+                                dict(inflight=0), dict(inflight=9), dict(wg_domains=-1), dict(reserved=3)])
+def test_server_config_validated(spkmc, kw):
+    cfg = _server_cfg(spkmc, **kw)
+    assert spkmc.lib.spkmc_server_reserved_bytes(C.byref(cfg)) == 0
+    h = C.c_void_p()
+    assert spkmc.lib.spkmc_server_create(C.byref(cfg), C.c_void_p(1 << 20), 1 << 30, None, C.byref(h)) == spkmc.E_INVAL
+    assert not h.value
+    assert spkmc.lib.spkmc_server_last_error(None)
+
+
+def test_server_pool_checked_before_any_device_call(spkmc):
+    cfg = _server_cfg(spkmc)
+    res = spkmc.lib.spkmc_server_reserved_bytes(C.byref(cfg))
+    assert res > 0 and res % 256 == 0
+    assert res >= spkmc.lib.spkmc_batch_workspace_bytes(16)
+    h = C.c_void_p()
+    assert spkmc.lib.spkmc_server_create(C.byref(cfg), None, 1 << 30, None, C.byref(h)) == spkmc.E_INVAL
+    assert spkmc.lib.spkmc_server_create(C.byref(cfg), C.c_void_p((1 << 20) + 8), 1 << 30, None,
+                                         C.byref(h)) == spkmc.E_INVAL
+    assert spkmc.lib.spkmc_server_create(C.byref(cfg), C.c_void_p(1 << 20), res - 1, None,
+                                         C.byref(h)) == spkmc.E_RANGE
+    assert not h.value
+
+
+def test_server_calls_reject_null(spkmc):
+    p = spkmc.make_params(32, 16)
+    rid = C.c_uint64()
+    assert spkmc.lib.spkmc_server_submit(None, C.byref(p), 10, 0, 0, -1.0, C.byref(rid)) == spkmc.E_INVAL
+    assert spkmc.lib.spkmc_server_step(None, 0, None) == spkmc.E_INVAL
+    assert spkmc.lib.spkmc_server_poll(None, 1, None) == spkmc.E_INVAL
+    assert spkmc.lib.spkmc_server_release(None, 1) == spkmc.E_INVAL
+    assert spkmc.lib.spkmc_server_clock(None) == 0.0
+    spkmc.lib.spkmc_server_destroy(None)
