@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--replicas", type=int, default=256, help="batch / serve: lattices in the replica mix")
     ap.add_argument("--cycles", type=int, default=1000, help="batch / serve: cycles per lattice")
     ap.add_argument("--macro-cycles", type=int, default=100, help="serve: cycles per macro-step")
-    ap.add_argument("--engine", default="auto", choices=["auto", "cycle", "persistent"])
+    ap.add_argument("--engine", default="auto", choices=["auto", "cycle", "persistent", "incremental"])
     ap.add_argument("--wg-domains", type=int, default=0)
     ap.add_argument("--obs-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -296,7 +296,7 @@ def main():
     secs = gpu_ms / 1e3
     value = fired / secs
     bytes_cycle = info["bytes_per_cycle"]
-    launches = 1 if info["engine"] == spkmc.ENGINES["persistent"] else 3 * args.steps
+    launches = 1 if info["engine"] in (spkmc.ENGINES["persistent"], spkmc.ENGINES["incremental"]) else 3 * args.steps
     achieved = bytes_cycle * args.steps / secs / 1e9
     traffic, traffic_rec = (None, None)
     if launches == 1:
@@ -316,7 +316,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "L": w["L"], "domain": w["domain"], "T": w["T"], "J": w["J"],
                    "H": w["H"], "rates": w["rates"], "init": w["init"], "seed": w["seed"],
-                   "layout": w["layout"], "engine": ["auto", "cycle", "persistent"][info["engine"]],
+                   "layout": w["layout"], "engine": ["auto", "cycle", "persistent", "incremental"][info["engine"]],
                    "grid": info["grid"], "block": info["block"], "wg_domains": info["wg_domains"],
                    "K": info["K"], "h": info["h"], "obs_every": args.obs_every},
         "attempts_per_s": (fired + nulls) / secs,

@@ -78,12 +78,18 @@ enum { SPKMC_INIT_RANDOM = 0, SPKMC_INIT_UP = 1, SPKMC_INIT_DOWN = 2 };
  * PACKED: one bit per site, octant-major (domain k, colour s, canonical q), plus a
  * copy of the 6 faces of every octant; needs h % 4 == 0. */
 enum { SPKMC_LAYOUT_INT8 = 0, SPKMC_LAYOUT_PACKED = 1 };
-/* Kernel engine.  AUTO picks PERSISTENT when supported, else CYCLE.
+/* Kernel engine.  AUTO picks PERSISTENT when supported (and when the domains
+ * fit in one resident launch), else CYCLE.
  * CYCLE: three launches per cycle (bin, select-and-flip, finalize), any layout.
- * PERSISTENT: one cooperative launch per spkmc_run call with device-wide
- * barriers between the phases of every cycle (PACKED layout, h = 8 or 16).
- * Both engines produce bit-identical trajectories. */
-enum { SPKMC_ENGINE_AUTO = 0, SPKMC_ENGINE_CYCLE = 1, SPKMC_ENGINE_PERSISTENT = 2 };
+ * PERSISTENT: one cooperative launch per spkmc_run call with a device-wide R_max
+ * exchange every cycle (PACKED layout, h = 8 or 16); every cycle bins the
+ * active octant of every domain afresh.
+ * INCREMENTAL: the persistent launch, but the class histograms of all octants
+ * stay on chip and follow every flip (the flipped site and its six neighbours
+ * change class); a cycle classifies its active octant only to locate the
+ * selected site, while the R_max exchange is in flight.
+ * All engines produce bit-identical trajectories. */
+enum { SPKMC_ENGINE_AUTO = 0, SPKMC_ENGINE_CYCLE = 1, SPKMC_ENGINE_PERSISTENT = 2, SPKMC_ENGINE_INCREMENTAL = 3 };
 
 typedef struct spkmc_params {
     uint32_t struct_size; /* sizeof(spkmc_params): ABI check                           */

@@ -11,9 +11,10 @@ hipError_t launch_faces(const Geom &g, hipStream_t stream);
 hipError_t launch_observables(const Geom &g, hipStream_t stream);
 hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream_t stream);
 bool persistent_supported(const Geom &g, const spkmc_params &p, std::string &why);
-hipError_t persistent_configure(const Geom &g, const spkmc_params &p, int &grid, int &block, int &wg_domains);
+hipError_t persistent_configure(const Geom &g, const spkmc_params &p, bool inc, int &grid, int &block,
+                                int &wg_domains);
 hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid,
-                             int block, int wg_domains, hipStream_t stream);
+                             int block, int wg_domains, bool inc, hipStream_t stream);
 uint64_t persistent_scratch_words(uint64_t K);
 struct Replica;
 size_t replica_bytes();
@@ -42,6 +43,9 @@ namespace spkmc {
 // Workgroups the batch kernel for octant edge h with P passes can keep resident
 // at once on the current device (0 on error).
 uint32_t batch_capacity(int h, int P);
+// Rows (domains per pass) and the most passes of the persistent kernels.
+int persist_rows(int h, bool inc);
+int persist_max_passes(int h, bool inc);
 uint32_t batch_wgs(const Geom &g, int P);
 
 // The observables of a lattice of N sites with parameters p from a copy of its

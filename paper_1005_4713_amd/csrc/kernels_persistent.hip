@@ -273,7 +273,9 @@ __device__ __forceinline__ void load16(const Geom &g, uint32_t k, int s, bool va
     r.zw = ld32((l < 8 ? hf.lo[2] : hf.hi[2]) + (l & 7));
 }
 
-// zrow: this row's 24 LDS words: face below (8), face above (8), zeros (8)
+// zrow: this row's 24 LDS words: face below (8), face above (8), zeros (8).
+// MOM: also accumulate the 13 popcount moments of the octant.
+template <bool MOM>
 __device__ __forceinline__ void compute16(const Raw<16> &r, bool valid, int l, uint32_t *zrow, Planes<16> &P,
                                           uint32_t (&m)[13]) {
     zrow[l] = r.zw;  // the row's own lanes read these back (same wavefront)
@@ -299,7 +301,7 @@ __device__ __forceinline__ void compute16(const Raw<16> &r, bool valid, int l, u
         P.b0[p] = o0;
         P.b1[p] = o1;
         P.b2[p] = o2;
-        if (valid) moments(w, o0, o1, o2, m);
+        if (MOM && valid) moments(w, o0, o1, o2, m);
     }
 }
 
@@ -324,6 +326,7 @@ __device__ __forceinline__ void load8(const Geom &g, uint32_t k, int s, bool val
     if (lz == 0) r.zface = ld32(hf.lo[2] + p);
     if (lz == 7) r.zface = ld32(hf.hi[2] + p);
 }
+template <bool MOM>
 __device__ __forceinline__ void compute8(const Raw<8> &r, bool valid, int l, uint32_t *, Planes<8> &P,
                                          uint32_t (&m)[13]) {
     int lz = l >> 1, p = l & 1;
@@ -344,7 +347,7 @@ __device__ __forceinline__ void compute8(const Raw<8> &r, bool valid, int l, uin
     P.b0[0] = o0;
     P.b1[0] = o1;
     P.b2[0] = o2;
-    if (valid) moments(w, o0, o1, o2, m);
+    if (MOM && valid) moments(w, o0, o1, o2, m);
 }
 
 template <int H>
@@ -353,11 +356,94 @@ __device__ __forceinline__ void load_octant(const Geom &g, uint32_t k, int s, bo
     if constexpr (H == 16) load16(g, k, s, valid, l, nb, r);
     else load8(g, k, s, valid, l, nb, r);
 }
-template <int H>
+template <int H, bool MOM>
 __device__ __forceinline__ void compute_octant(const Raw<H> &r, bool valid, int l, uint32_t *zrow, Planes<H> &P,
                                                uint32_t (&m)[13]) {
-    if constexpr (H == 16) compute16(r, valid, l, zrow, P, m);
-    else compute8(r, valid, l, zrow, P, m);
+    if constexpr (H == 16) compute16<MOM>(r, valid, l, zrow, P, m);
+    else compute8<MOM>(r, valid, l, zrow, P, m);
+}
+
+// ---------------------------------------------------------------------------
+// Incremental class histograms (the class changes a flip causes, step 6)
+// ---------------------------------------------------------------------------
+// Class of a site from its spin (1 = up) and its number of up neighbours: an up
+// spin is aligned with its up neighbours, a down spin with the others.
+__device__ __forceinline__ int site_class(uint32_t up, int nup) { return up ? 7 + nup : 6 - nup; }
+
+// Packed counts: class c in the 16-bit half (c & 1) of word c >> 1 (h^3 <= 4096).
+__device__ __forceinline__ uint32_t hcount(const uint32_t *hp, int c) {
+    return (hp[c >> 1] >> (16 * (c & 1))) & 0xFFFFu;
+}
+__device__ __forceinline__ void hadd(uint32_t *hp, int c, int v) {  // a count never drops below 0
+    atomicAdd(&hp[c >> 1], (uint32_t)v << (16 * (c & 1)));
+}
+// A site leaves class c_old for c_new.
+__device__ __forceinline__ void hmove(uint32_t *hp, int c_old, int c_new) {
+    hadd(hp, c_old, -1);
+    hadd(hp, c_new, 1);
+}
+
+// Where site (x, y, z) of an octant sits in the class planes of a row: lane,
+// word and bit (h = 16: lane z, word y / 2; h = 8: lane 2 z + y / 4, one word).
+template <int H>
+__device__ __forceinline__ void plane_loc(int x, int y, int z, int &lane, int &word, int &bit) {
+    if constexpr (H == 16) {
+        lane = z;
+        word = y >> 1;
+        bit = x + 16 * (y & 1);
+    } else {
+        lane = 2 * z + (y >> 2);
+        word = 0;
+        bit = x + 8 * (y & 3);
+    }
+}
+
+// Spin (1 = up) of the site at domain-local coordinates T (each in [-2h, 4h))
+// of the domain at c; coordinates outside [0, 2h) belong to the periodic
+// neighbour domain.  Sets the domain and octant of the site.
+template <int H>
+__device__ __forceinline__ uint32_t spin_at(const Geom &g, DomainCoord c, const int (&T)[3], uint32_t &k, int &o) {
+    int kc[3] = {c.kx, c.ky, c.kz}, X[3];
+    o = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        X[a] = T[a];
+        if (X[a] < 0) {
+            X[a] += 2 * H;
+            kc[a] = wrapm(kc[a], g.nd);
+        } else if (X[a] >= 2 * H) {
+            X[a] -= 2 * H;
+            kc[a] = wrapp(kc[a], g.nd);
+        }
+        o |= (X[a] >= H) << a;
+    }
+    k = dindex(kc[0], kc[1], kc[2], g.nd);
+    const uint32_t q = (uint32_t)((X[0] & (H - 1)) + H * ((X[1] & (H - 1)) + H * (X[2] & (H - 1))));
+    const uint32_t word = (k * 8u + (uint32_t)o) * (uint32_t)(H * H * H / 32) + (q >> 5);  // < N / 32 < 2^31
+    return (ld32(&g.A[word]) >> (q & 31)) & 1u;
+}
+
+// Class changes pushed to a domain of another workgroup: per (domain, octant,
+// spin) one 64-bit word holding 7 signed base-512 digits, digit a = the net
+// change of the class with aligned count a.  Pushes are atomic adds; the owner
+// takes the word with an exchange and recovers the digits (each stays within
+// +-255: at most one push reaches an octant per cycle, and every octant is
+// folded at least once per kFoldAll cycles).
+constexpr uint64_t kFoldAll = 64;
+__device__ __forceinline__ uint64_t digit_move(int a_old, int a_new) {
+    return (1ull << (9 * a_new)) - (1ull << (9 * a_old));
+}
+// Fold a taken word into the packed counts of spin half `up`; false if the
+// word was not a sum of in-range digits.
+__device__ __forceinline__ bool fold_word(uint64_t v, int up, uint32_t *hp) {
+    int64_t V = (int64_t)v;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        const int64_t dig = ((V & 511) ^ 256) - 256;
+        V = (V - dig) >> 9;
+        if (dig) hadd(hp, 7 * up + i, (int)dig);
+    }
+    return V == 0;
 }
 
 // Inclusive prefix sum over the 16 lanes of a DPP row (lane 15 ends with the
@@ -394,7 +480,8 @@ __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memr
 struct PersistShared {
     double r[14];                      // rate table
     uint32_t mom[kMaxWgDomains][13];   // per domain: the 13 popcount moments of its active octant
-    uint32_t hist[kMaxWgDomains][14];  // per domain: class histogram
+    uint32_t hist[kMaxWgDomains][14];  // per domain: class histogram (re-binning engine)
+    uint32_t histp[kMaxWgDomains][8][7];  // per domain and octant: packed class counts (incremental engine)
     double acc[kMaxWgDomains][14];     // per domain: running FP64 sums of the frequency line
     double rk[kMaxWgDomains];
     uint32_t zbuf[64][24];             // per row: z face words below (8), above (8), zeros (8)
@@ -449,7 +536,47 @@ __device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch 
     }
 }
 
+// Bin octant o of every domain of the workgroup (the 13 moments of each row, then
+// its histogram) into the packed counts of that octant.
 template <int H, int P, int BLOCK>
+__device__ __forceinline__ void bin_all(const Geom &g, uint32_t kbase, uint32_t nvalid, int o, PersistShared &sh) {
+    constexpr int rows = BLOCK / 16;
+    const int tid = threadIdx.x, row = tid >> 4, l = tid & 15;
+    constexpr uint32_t D = (uint32_t)(rows * P);
+#pragma unroll
+    for (int pp = 0; pp < P; ++pp) {
+        const uint32_t ld = (uint32_t)(pp * rows + row);
+        const bool valid = ld < nvalid;
+        Raw<H> raw;
+        Planes<H> pl;
+        load_octant<H>(g, kbase + ld, o, valid, l, sh.nbdom[valid ? ld : 0], raw);
+        uint32_t m[13];
+#pragma unroll
+        for (int i = 0; i < 13; ++i) m[i] = 0;
+        compute_octant<H, true>(raw, valid, l, sh.zbuf[row], pl, m);
+#pragma unroll
+        for (int i = 0; i < 13; ++i) m[i] = row_scan(m[i]);
+        if (l == 15) {
+#pragma unroll
+            for (int i = 0; i < 13; ++i) sh.mom[ld][i] = m[i];
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = (uint32_t)tid; i < D; i += BLOCK) {
+        uint32_t mm[13], hc[14];
+        for (int c = 0; c < 13; ++c) mm[c] = sh.mom[i][c];
+        hist_from_moments(mm, g.h3, hc);
+        for (int c = 0; c < 14; c += 2) sh.histp[i][o][c >> 1] = i < nvalid ? (hc[c] | (hc[c + 1] << 16)) : 0u;
+    }
+    __syncthreads();
+}
+
+// INC = true: class histograms of all eight octants of every domain stay in LDS
+// for the whole launch and follow every flip (the flipped site and its six
+// neighbours change class, step 6); the active octant is classified only to
+// find the selected site, while the R_max exchange is in flight.
+// INC = false: the active octant of every domain is binned afresh each cycle.
+template <int H, int P, int BLOCK, bool INC>
 __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t gid, PersistShared &sh) {
     const Geom &g = R.g;
     const PersistScratch &xs = R.xs;
@@ -500,6 +627,13 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     }
     __syncthreads();
 
+    // INC: the histograms of all eight octants, from the spins at launch start
+    // (no workgroup flips before every workgroup has published its first R_max)
+    if constexpr (INC) {
+#pragma unroll 1
+        for (int o = 0; o < 8; ++o) bin_all<H, P, BLOCK>(g, kbase, nvalid, o, sh);
+    }
+
     DevState *st = g.st;
     // launch-start totals (read before any workgroup can publish its first slot,
     // hence before any workgroup can fold its own totals in at the end)
@@ -540,56 +674,107 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         }
         prev_colour = s;
 
-        // --- steps 1 and 4a: class planes and moments of the active octants
         Planes<H> pl[P];
-        Raw<H> raw[2];
-        load_octant<H>(g, kbase + (uint32_t)row, s, (uint32_t)row < nvalid, l, sh.nbdom[row], raw[0]);
-#pragma unroll
-        for (int pp = 0; pp < P; ++pp) {
-            uint32_t ld = (uint32_t)(pp * rows + row);
-            bool valid = ld < nvalid;
-            if (pp + 1 < P) {  // next pass's words in flight while this pass computes
-                uint32_t ldn = ld + (uint32_t)rows;
-                load_octant<H>(g, kbase + ldn, s, ldn < nvalid, l, sh.nbdom[ldn < nvalid ? ldn : 0], raw[(pp + 1) & 1]);
+        if constexpr (INC) {
+            // --- fold the class changes other workgroups pushed into octant s (and,
+            // every kFoldAll cycles, into all octants)
+            const bool fold_all = (n - n0) % kFoldAll == kFoldAll - 1;
+#pragma unroll 1
+            for (int o = 0; o < 8; ++o) {
+                if (o != s && !fold_all) continue;
+                for (uint32_t i = tid; i < 2 * nvalid; i += nthr) {
+                    uint64_t *w = g.dh + ((uint64_t)(kbase + (i >> 1)) * 8 + o) * 2 + (i & 1);
+                    uint64_t v = ld64(w);
+                    if (v) {
+                        v = __hip_atomic_exchange(w, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (!fold_word(v, (int)(i & 1), sh.histp[i >> 1][o])) atomicOr(&st->error, kErrHist);
+                    }
+                }
             }
-            uint32_t m[13];
-#pragma unroll
-            for (int i = 0; i < 13; ++i) m[i] = 0;
-            compute_octant<H>(raw[pp & 1], valid, l, sh.zbuf[row], pl[pp], m);
-#pragma unroll
-            for (int i = 0; i < 13; ++i) m[i] = row_scan(m[i]);
-            if (l == 15) {
-#pragma unroll
-                for (int i = 0; i < 13; ++i) sh.mom[ld][i] = m[i];
+            __syncthreads();
+            // --- step 1: frequency line of every domain from its counts
+            for (uint32_t i = tid; i < D; i += nthr) {
+                const uint32_t *hp = sh.histp[i][s];
+                double a = 0.0;
+                for (int c = 0; c < 14; ++c) {
+                    double term = (double)hcount(hp, c) * sh.r[c];
+                    a = a + term;
+                    sh.acc[i][c] = a;
+                }
+                sh.rk[i] = i < nvalid ? a : 0.0;
             }
+            __syncthreads();
+        } else {
+            // --- steps 1 and 4a: class planes and moments of the active octants
+            Raw<H> raw[2];
+            load_octant<H>(g, kbase + (uint32_t)row, s, (uint32_t)row < nvalid, l, sh.nbdom[row], raw[0]);
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                uint32_t ld = (uint32_t)(pp * rows + row);
+                bool valid = ld < nvalid;
+                if (pp + 1 < P) {  // next pass's words in flight while this pass computes
+                    uint32_t ldn = ld + (uint32_t)rows;
+                    load_octant<H>(g, kbase + ldn, s, ldn < nvalid, l, sh.nbdom[ldn < nvalid ? ldn : 0],
+                                   raw[(pp + 1) & 1]);
+                }
+                uint32_t m[13];
+#pragma unroll
+                for (int i = 0; i < 13; ++i) m[i] = 0;
+                compute_octant<H, true>(raw[pp & 1], valid, l, sh.zbuf[row], pl[pp], m);
+#pragma unroll
+                for (int i = 0; i < 13; ++i) m[i] = row_scan(m[i]);
+                if (l == 15) {
+#pragma unroll
+                    for (int i = 0; i < 13; ++i) sh.mom[ld][i] = m[i];
+                }
+            }
+            __syncthreads();
+            // step 1: histogram and frequency line of every domain of the workgroup,
+            // running sums kept for the selection (the same sums in the same order)
+            for (uint32_t i = tid; i < D; i += nthr) {
+                uint32_t mm[13], hc[14];
+                for (int c = 0; c < 13; ++c) mm[c] = sh.mom[i][c];
+                hist_from_moments(mm, g.h3, hc);
+                double a = 0.0;
+                for (int c = 0; c < 14; ++c) {
+                    double term = (double)hc[c] * sh.r[c];
+                    a = a + term;
+                    sh.acc[i][c] = a;
+                    sh.hist[i][c] = hc[c];
+                }
+                sh.rk[i] = i < nvalid ? a : 0.0;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        // step 1: histogram and frequency line of every domain of the workgroup,
-        // running sums kept for the selection (the same sums in the same order)
-        for (uint32_t i = tid; i < D; i += nthr) {
-            uint32_t mm[13], hc[14];
-            for (int c = 0; c < 13; ++c) mm[c] = sh.mom[i][c];
-            hist_from_moments(mm, g.h3, hc);
-            double a = 0.0;
-            for (int c = 0; c < 14; ++c) {
-                double term = (double)hc[c] * sh.r[c];
-                a = a + term;
-                sh.acc[i][c] = a;
-                sh.hist[i][c] = hc[c];
-            }
-            sh.rk[i] = i < nvalid ? a : 0.0;
-        }
-        __syncthreads();
 
         // --- step 2: R_max over all active octants
+        // bank n & 1 holds cycles n - 2 and n; the generation bit tells them apart
+        uint64_t *bank = xs.slot + (n & 1) * (uint64_t)G;
+        const uint64_t gen = ((n >> 1) & 1) << 63;
         if (tid < 64) {
             double v = 0.0;
             for (uint32_t i = tid; i < D; i += 64) v = fmax(v, sh.rk[i]);
             for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-            // bank n & 1 holds cycles n - 2 and n; the generation bit tells them apart
-            uint64_t *bank = xs.slot + (n & 1) * (uint64_t)G;
-            const uint64_t gen = ((n >> 1) & 1) << 63;
             if (tid == 0) st64(&bank[gid], double_to_bits(v) | gen);
+        }
+        if constexpr (INC) {
+            // the active octants' class planes, while the other maxima travel
+            Raw<H> raw[2];
+            load_octant<H>(g, kbase + (uint32_t)row, s, (uint32_t)row < nvalid, l, sh.nbdom[row], raw[0]);
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                uint32_t ld = (uint32_t)(pp * rows + row);
+                bool valid = ld < nvalid;
+                if (pp + 1 < P) {
+                    uint32_t ldn = ld + (uint32_t)rows;
+                    load_octant<H>(g, kbase + ldn, s, ldn < nvalid, l, sh.nbdom[ldn < nvalid ? ldn : 0],
+                                   raw[(pp + 1) & 1]);
+                }
+                uint32_t m[13];
+                compute_octant<H, false>(raw[pp & 1], valid, l, sh.zbuf[row], pl[pp], m);
+            }
+        }
+        if (tid < 64) {
             // workgroup 0 sums a record stored two or more cycles ago while it waits
             if (recorder && sh.pend_head != sh.pend_tail && sh.pend_cycle[sh.pend_head % kRecBanks] + 2 <= n + 1)
                 emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
@@ -654,7 +839,9 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             const uint64_t bal = __ballot(hit);
             const uint32_t rowbits = (uint32_t)(bal >> (16 * (row & 3))) & 0xFFFFu;
             const int cs = rowbits ? __builtin_ctz(rowbits) : -1;
-            const uint32_t j = cs >= 0 ? mul_index(uz, sh.hist[ld][cs]) : 0u;
+            uint32_t ncs = 0;
+            if (cs >= 0) ncs = INC ? hcount(sh.histp[ld][s], cs) : sh.hist[ld][cs];
+            const uint32_t j = cs >= 0 ? mul_index(uz, ncs) : 0u;
             // class cs as (spin, n_up pattern): up spin: n_up = a; down spin: n_up = 6 - a
             const int up = cs >= 7, aa = cs >= 0 ? cs % 7 : 0, v = up ? aa : 6 - aa;
             const uint32_t es = up ? 0u : 0xFFFFFFFFu;  // bits that must be 0 after the xor
@@ -694,11 +881,66 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             }
         }
         __syncthreads();
-        // --- the flips of this cycle, one thread each
-        for (uint32_t i = tid; i < sh.nflip; i += nthr) {
+        // --- the flips of this cycle
+        // incremental engine: three threads per flip, one per axis, each moving the
+        // classes of the flipped site's two neighbours along its axis; the first
+        // also flips the site (spin word and face copies) and moves its class
+        const uint32_t nwork = INC ? 3 * sh.nflip : sh.nflip;
+        for (uint32_t t = tid; t < nwork; t += nthr) {
+            const uint32_t i = INC ? t / 3 : t, ax = INC ? t % 3 : 0;
             const uint32_t f = sh.flipq[i];
             const uint32_t ld = f >> 16, cs = (f >> 12) & 15u, q = f & 0xFFFu;
             const uint32_t k = kbase + ld;
+            if constexpr (INC) {
+                // The neighbours' other neighbours do not change in this cycle (one flip
+                // per domain, and same-coloured octants of different domains never
+                // touch), so their classes follow from spins read now, with the flipped
+                // site's spin taken before its flip.  The twelve reads are independent.
+                const int qc[3] = {(int)(q % H), (int)((q / H) % H), (int)(q / (H * H))};
+                const int Q[3] = {(s & 1) * H + qc[0], ((s >> 1) & 1) * H + qc[1], ((s >> 2) & 1) * H + qc[2]};
+                const uint32_t up = cs >= 7;
+                const int dn = up ? -1 : 1;  // change of the neighbours' up counts
+                const DomainCoord dc = dcoord(k, g.nd);
+                const int b1 = ax == 0 ? 1 : 0, b2 = ax == 2 ? 1 : 2;  // the other two axes
+                uint32_t sj[2], kj[2];
+                int oj[2], nup[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int side = e ? 1 : -1;
+                    int J[3] = {Q[0], Q[1], Q[2]};
+                    J[ax] += side;
+                    uint32_t kt;
+                    int ot;
+                    sj[e] = spin_at<H>(g, dc, J, kj[e], oj[e]);
+                    nup[e] = (int)up;
+                    int T[3] = {J[0], J[1], J[2]};
+                    T[ax] += side;
+                    nup[e] += (int)spin_at<H>(g, dc, T, kt, ot);
+                    T[ax] = J[ax];
+                    T[b1] -= 1;
+                    nup[e] += (int)spin_at<H>(g, dc, T, kt, ot);
+                    T[b1] += 2;
+                    nup[e] += (int)spin_at<H>(g, dc, T, kt, ot);
+                    T[b1] = J[b1];
+                    T[b2] -= 1;
+                    nup[e] += (int)spin_at<H>(g, dc, T, kt, ot);
+                    T[b2] += 2;
+                    nup[e] += (int)spin_at<H>(g, dc, T, kt, ot);
+                }
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int c_old = site_class(sj[e], nup[e]), c_new = site_class(sj[e], nup[e] + dn);
+                    if (kj[e] - kbase < nvalid) {
+                        hmove(sh.histp[kj[e] - kbase][oj[e]], c_old, c_new);
+                    } else {
+                        (void)__hip_atomic_fetch_add(g.dh + ((uint64_t)kj[e] * 8 + oj[e]) * 2 + sj[e],
+                                                     digit_move(c_old - 7 * (int)sj[e], c_new - 7 * (int)sj[e]),
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                if (ax != 0) continue;
+                hmove(sh.histp[ld][s], cs, site_class(!up, up ? cs - 7 : 6 - cs));
+            }
             flip_word(g.A + ((uint64_t)k * 8 + s) * g.wpo + (q >> 5), 1u << (q & 31));
             const uint32_t lx = q % H, ly = (q / H) % H, lz = q / (H * H);
             uint32_t *F = g.F + ((uint64_t)k * 8 + s) * g.fwpo;
@@ -818,15 +1060,15 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
 }
 
 // One lattice: the descriptor by value.
-template <int H, int P, int BLOCK>
+template <int H, int P, int BLOCK, bool INC>
 __global__ void __launch_bounds__(BLOCK) k_persistent(Replica R) {
     __shared__ PersistShared sh;
-    persistent_body<H, P, BLOCK>(R, blockIdx.x, sh);
+    persistent_body<H, P, BLOCK, INC>(R, blockIdx.x, sh);
 }
 
 // Many independent lattices in one launch: each workgroup finds its lattice by
 // its workgroup index; lattices never wait for one another.
-template <int H, int P, int BLOCK>
+template <int H, int P, int BLOCK, bool INC>
 __global__ void __launch_bounds__(BLOCK) k_persistent_batch(const Replica *__restrict__ reps, uint32_t nrep) {
     __shared__ PersistShared sh;
     uint32_t lo = 0, hi = nrep;  // last replica with first_wg <= blockIdx.x
@@ -838,7 +1080,7 @@ __global__ void __launch_bounds__(BLOCK) k_persistent_batch(const Replica *__res
     // the index is the same in every lane: keep the descriptor in scalar registers
     const Replica &R = reps[__builtin_amdgcn_readfirstlane(lo)];
     if (blockIdx.x >= R.first_wg + R.G) return;  // a spare workgroup past the last lattice
-    persistent_body<H, P, BLOCK>(R, blockIdx.x - R.first_wg, sh);
+    persistent_body<H, P, BLOCK, INC>(R, blockIdx.x - R.first_wg, sh);
 }
 
 // Before a launch: slots carry the generation of no cycle of this launch yet,
@@ -848,76 +1090,92 @@ __device__ __forceinline__ void prep_one(const PersistScratch &xs, uint32_t G, u
     for (uint64_t nb = n0; nb < n0 + 2; ++nb) xs.slot[(nb & 1) * G + i] = (((nb >> 1) + 1) & 1) << 63;
     xs.flag[i] = n0;
 }
-__global__ void k_persistent_prep(PersistScratch xs, uint32_t G, uint64_t n0) {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < G) prep_one(xs, G, n0, i);
+// and (incremental engine) no pushed class changes pending: the launch starts
+// from histograms binned afresh.
+__global__ void k_persistent_prep(PersistScratch xs, uint32_t G, uint64_t n0, uint64_t *dh, uint64_t ndh) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < G) prep_one(xs, G, n0, (uint32_t)i);
+    for (uint64_t w = i; w < ndh; w += (uint64_t)gridDim.x * blockDim.x) dh[w] = 0;
 }
-__global__ void k_persistent_prep_batch(const Replica *__restrict__ reps, uint32_t nrep) {
-    for (uint32_t r = blockIdx.x; r < nrep; r += gridDim.x)
+__global__ void k_persistent_prep_batch(const Replica *__restrict__ reps, uint32_t nrep, int zero_dh) {
+    for (uint32_t r = blockIdx.x; r < nrep; r += gridDim.x) {
         for (uint32_t i = threadIdx.x; i < reps[r].G; i += blockDim.x) prep_one(reps[r].xs, reps[r].G, reps[r].n0, i);
+        if (zero_dh) {
+            const uint64_t ndh = (uint64_t)reps[r].g.K * 16;
+            for (uint64_t w = threadIdx.x; w < ndh; w += blockDim.x) reps[r].g.dh[w] = 0;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-// Launch shapes: h = 16 keeps up to 4 passes of 32 domains in registers with
-// 512 threads (two waves per SIMD, 256 registers each); h = 8 needs 4
-// registers per pass and runs 1024 threads.
+// Launch shapes.  A 16-lane row owns a domain; a workgroup runs `rows` rows
+// and P passes (1, 2 or 4).  h = 16 keeps up to four passes of class planes in
+// 256 registers with 32 rows (512 threads, two waves per SIMD); h = 8 needs 4
+// registers per pass and runs 64 rows (1024 threads, four waves per SIMD).
+int persist_rows(int h, bool) { return h == 8 ? 64 : 32; }
+int persist_max_passes(int, bool) { return 4; }
+
 template <int H, int P, int BLOCK>
-static void *kernel_ptr(bool batch) {
-    return batch ? reinterpret_cast<void *>(&k_persistent_batch<H, P, BLOCK>)
-                 : reinterpret_cast<void *>(&k_persistent<H, P, BLOCK>);
+static void *kernel_of(bool batch, bool inc) {
+    if (inc) return reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, true>);
+    return batch ? reinterpret_cast<void *>(&k_persistent_batch<H, P, BLOCK, false>)
+                 : reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false>);
 }
-static void *select_kernel(int h, int P, int block, bool batch = false) {
+// Batches use the re-binning kernel.
+static void *select_kernel(int h, int P, int block, bool batch = false, bool inc = false) {
+    if (batch && inc) return nullptr;
     if (h == 16 && block == 512)
-        return P == 1 ? kernel_ptr<16, 1, 512>(batch) : P == 2 ? kernel_ptr<16, 2, 512>(batch)
-                                                               : kernel_ptr<16, 4, 512>(batch);
+        return P == 1 ? kernel_of<16, 1, 512>(batch, inc) : P == 2 ? kernel_of<16, 2, 512>(batch, inc)
+               : P == 4 ? kernel_of<16, 4, 512>(batch, inc) : nullptr;
     if (h == 8 && block == 1024)
-        return P == 1 ? kernel_ptr<8, 1, 1024>(batch) : P == 2 ? kernel_ptr<8, 2, 1024>(batch)
-                                                               : kernel_ptr<8, 4, 1024>(batch);
+        return P == 1 ? kernel_of<8, 1, 1024>(batch, inc) : P == 2 ? kernel_of<8, 2, 1024>(batch, inc)
+               : P == 4 ? kernel_of<8, 4, 1024>(batch, inc) : nullptr;
     return nullptr;
 }
 
 bool persistent_supported(const Geom &g, const spkmc_params &p, std::string &why) {
     if (g.layout != SPKMC_LAYOUT_PACKED) { why = "needs the PACKED layout"; return false; }
     if (g.h != 8 && g.h != 16) { why = "needs an octant edge of 8 or 16 (domain 16 or 32)"; return false; }
-    const int rows = g.h == 16 ? 32 : 64;
+    const bool inc = p.engine == SPKMC_ENGINE_INCREMENTAL;
+    const int rows = persist_rows(g.h, inc), pmax = persist_max_passes(g.h, inc);
     const int pc = p.wg_domains / rows;
-    if (p.wg_domains && (p.wg_domains % rows || pc > 4 || (pc & (pc - 1)))) {
-        why = "wg_domains must be 32, 64 or 128 (h = 16) or 64, 128 or 256 (h = 8)";
+    if (p.wg_domains && (p.wg_domains % rows || pc > pmax || (pc & (pc - 1)))) {
+        why = "wg_domains must be " + std::to_string(rows) + " times 1, 2" + (pmax == 4 ? " or 4" : "") +
+              " for this octant edge and engine";
         return false;
     }
     return true;
 }
 
-hipError_t persistent_configure(const Geom &g, const spkmc_params &p, int &grid, int &block, int &wg_domains) {
+hipError_t persistent_configure(const Geom &g, const spkmc_params &p, bool inc, int &grid, int &block,
+                                int &wg_domains) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     int cus = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const int rows = g.h == 16 ? 32 : 64;  // domains per pass
-    int P = 0;
+    const int rows = persist_rows(g.h, inc), pmax = persist_max_passes(g.h, inc);
     block = rows * 16;
-    if (p.wg_domains) {
-        P = p.wg_domains / rows;
-    } else {
-        // the fewest passes that keep every workgroup resident (one per CU at most)
-        P = 1;
-        while (P < 4 && (g.K + (uint64_t)rows * P - 1) / ((uint64_t)rows * P) > (uint64_t)cus) P <<= 1;
+    // the fewest passes whose workgroups are all resident at once (or the
+    // requested domains per workgroup)
+    for (int P = 1; P <= pmax; P <<= 1) {
+        if (p.wg_domains && p.wg_domains != rows * P) continue;
+        void *kern = select_kernel(g.h, P, block, false, inc);
+        if (!kern) return hipErrorInvalidValue;
+        int occ = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, 0);
+        if (e != hipSuccess) return e;
+        const uint64_t D = (uint64_t)rows * P, G = (g.K + D - 1) / D;
+        if (occ > 0 && G <= (uint64_t)occ * cus && G <= (uint64_t)kMaxGrid) {
+            grid = (int)G;
+            wg_domains = (int)D;
+            return hipSuccess;
+        }
     }
-    void *kern = select_kernel(g.h, P, block);
-    if (!kern) return hipErrorInvalidValue;
-    int occ = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, 0);
-    if (e != hipSuccess) return e;
-    uint64_t D = (uint64_t)rows * P;
-    uint64_t G = (g.K + D - 1) / D;
-    if (occ <= 0 || G > (uint64_t)occ * cus || G > (uint64_t)kMaxGrid) return hipErrorCooperativeLaunchTooLarge;
-    grid = (int)G;
-    wg_domains = (int)D;
-    return hipSuccess;
+    return hipErrorCooperativeLaunchTooLarge;
 }
 
 uint64_t persistent_scratch_words(uint64_t K) { return kScratchWordsPerWg * (K / 16 + 2) + 16; }
@@ -931,12 +1189,15 @@ PersistScratch scratch_of(const Geom &g, int G) {
 }
 
 hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid, int block,
-                             int wg_domains, hipStream_t stream) {
+                             int wg_domains, bool inc, hipStream_t stream) {
     PersistScratch xs = scratch_of(g, grid);
     int P = wg_domains / (block / 16);
-    void *kern = select_kernel(g.h, P, block);
+    void *kern = select_kernel(g.h, P, block, false, inc);
     if (!kern) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_persistent_prep, dim3((grid + 255) / 256), dim3(256), 0, stream, xs, (uint32_t)grid, n0);
+    const uint64_t ndh = inc ? (uint64_t)g.K * 16 : 0;
+    uint64_t blocks = ((uint64_t)grid + 255) / 256, bdh = (ndh + 255) / 256;
+    blocks = blocks > bdh ? blocks : (bdh < 2048 ? bdh : 2048);
+    hipLaunchKernelGGL(k_persistent_prep, dim3((uint32_t)blocks), dim3(256), 0, stream, xs, (uint32_t)grid, n0, g.dh, ndh);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     Replica R;
@@ -959,14 +1220,14 @@ size_t replica_bytes() { return sizeof(Replica); }
 
 // Workgroups lattice i needs with `rows_pp` domains per pass and P passes.
 uint32_t batch_wgs(const Geom &g, int P) {
-    const uint64_t D = (uint64_t)(g.h == 16 ? 32 : 64) * P;
+    const uint64_t D = (uint64_t)persist_rows(g.h, false) * P;
     return (uint32_t)((g.K + D - 1) / D);
 }
 
 // Workgroups of the batch kernel for octant edge h and P passes that the
 // current device keeps resident at once (0 on error).
 uint32_t batch_capacity(int h, int P) {
-    const int block = h == 16 ? 512 : 1024;
+    const int block = persist_rows(h, false) * 16;
     void *kern = select_kernel(h, P, block, true);
     if (!kern) return 0;
     int dev = 0, cus = 0, occ = 0;
@@ -982,7 +1243,7 @@ hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t 
                       uint32_t n, int P, Replica *out, int &grid, int &block) {
     if (n == 0) return hipErrorInvalidValue;
     const int h = gs[0]->h;
-    block = h == 16 ? 512 : 1024;
+    block = persist_rows(h, false) * 16;
     void *kern = select_kernel(h, P, block, true);
     if (!kern) return hipErrorInvalidValue;
     uint32_t first = 0;
@@ -1033,7 +1294,7 @@ hipError_t upload_replicas(const Replica *host, uint32_t n, Replica *dev, hipStr
 hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipStream_t stream) {
     void *kern = select_kernel(h, P, block, true);
     if (!kern) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_persistent_prep_batch, dim3(n < 64 ? n : 64), dim3(256), 0, stream, dev_reps, n);
+    hipLaunchKernelGGL(k_persistent_prep_batch, dim3(n < 256 ? n : 256), dim3(256), 0, stream, dev_reps, n, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const Replica *reps = dev_reps;

@@ -50,7 +50,7 @@ static int make_rates(const spkmc_params *p, double out[14]) {
 }
 
 struct LayoutPlan {
-    size_t off_rates, off_rec, off_Rk, off_hist, off_flip, off_sync, off_spin, off_F, total, spin_bytes;
+    size_t off_rates, off_rec, off_Rk, off_hist, off_flip, off_sync, off_dh, off_spin, off_F, total, spin_bytes;
 };
 
 static bool validate(const spkmc_params *p, std::string &why) {
@@ -64,7 +64,7 @@ static bool validate(const spkmc_params *p, std::string &why) {
     if (p->rates != SPKMC_RATES_GLAUBER && p->rates != SPKMC_RATES_METROPOLIS) { why = "unknown rates"; return false; }
     if (p->init < 0 || p->init > 2) { why = "unknown init"; return false; }
     if (p->layout != SPKMC_LAYOUT_INT8 && p->layout != SPKMC_LAYOUT_PACKED) { why = "unknown layout"; return false; }
-    if (p->engine < 0 || p->engine > 2) { why = "unknown engine"; return false; }
+    if (p->engine < 0 || p->engine > 3) { why = "unknown engine"; return false; }
     if (p->wg_domains < 0) { why = "wg_domains must be >= 0"; return false; }
     int h = p->domain / 2;
     if (p->layout == SPKMC_LAYOUT_PACKED && (h % 4)) { why = "PACKED layout needs the octant edge (domain/2) to be a multiple of 4"; return false; }
@@ -85,8 +85,11 @@ static LayoutPlan plan(const spkmc_params *p) {
     lp.off_Rk = o; o = align256(o + K * 8);
     lp.off_hist = o; o = align256(o + K * 64);
     lp.off_flip = o; o = align256(o + K * 8);
-    // persistent engine: slots, flags and record partials of its workgroups
+    // persistent engine: slots, flags and record partials of its workgroups, and
+    // the class changes its workgroups push to one another (PACKED)
     lp.off_sync = o; o = align256(o + persistent_scratch_words(K) * 8);
+    lp.off_dh = o;
+    if (p->layout == SPKMC_LAYOUT_PACKED) o = align256(o + K * 16 * 8);
     lp.off_spin = o;
     if (p->layout == SPKMC_LAYOUT_INT8) {
         o = align256(o + N);
@@ -177,6 +180,7 @@ spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, 
     g.hist = (uint32_t *)(c->dev + lp.off_hist);
     g.flip = (uint64_t *)(c->dev + lp.off_flip);
     g.sync = (uint64_t *)(c->dev + lp.off_sync);
+    g.dh = p->layout == SPKMC_LAYOUT_PACKED ? (uint64_t *)(c->dev + lp.off_dh) : nullptr;
     if (p->layout == SPKMC_LAYOUT_INT8) {
         g.spin8 = (int8_t *)(c->dev + lp.off_spin);
     } else {
@@ -191,13 +195,17 @@ spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, 
     // engine choice
     std::string pwhy;
     bool pers = persistent_supported(g, *p, pwhy);
-    if (p->engine == SPKMC_ENGINE_PERSISTENT && !pers) return fail(c, SPKMC_E_UNSUPPORTED, "persistent engine: " + pwhy);
-    c->engine = (p->engine == SPKMC_ENGINE_CYCLE || !pers) ? SPKMC_ENGINE_CYCLE : SPKMC_ENGINE_PERSISTENT;
+    const bool want_pers = p->engine == SPKMC_ENGINE_PERSISTENT || p->engine == SPKMC_ENGINE_INCREMENTAL;
+    if (want_pers && !pers) return fail(c, SPKMC_E_UNSUPPORTED, "persistent engine: " + pwhy);
+    c->engine = (p->engine == SPKMC_ENGINE_CYCLE || !pers) ? SPKMC_ENGINE_CYCLE
+                : p->engine == SPKMC_ENGINE_INCREMENTAL ? SPKMC_ENGINE_INCREMENTAL
+                                                        : SPKMC_ENGINE_PERSISTENT;
     c->grid = (int)g.K;
     c->block = 256;
     c->wg_domains = 0;
-    if (c->engine == SPKMC_ENGINE_PERSISTENT) {
-        hipError_t e = persistent_configure(g, *p, c->grid, c->block, c->wg_domains);
+    if (c->engine != SPKMC_ENGINE_CYCLE) {
+        hipError_t e = persistent_configure(g, *p, c->engine == SPKMC_ENGINE_INCREMENTAL, c->grid, c->block,
+                                            c->wg_domains);
         if (e == hipErrorCooperativeLaunchTooLarge && p->engine == SPKMC_ENGINE_AUTO) {
             // more domains than one resident launch holds: the per-cycle engine
             c->engine = SPKMC_ENGINE_CYCLE;
@@ -226,8 +234,9 @@ spkmc_status spkmc_run(spkmc_ctx *c, uint64_t ncycles, uint32_t obs_every) {
     if (c->failed || !c->dev) return fail(c, SPKMC_E_STATE, "context is in a failed state");
     if (ncycles == 0) return SPKMC_OK;
     hipError_t e = hipSuccess;
-    if (c->engine == SPKMC_ENGINE_PERSISTENT) {
-        e = launch_persistent(c->g, c->cycle, ncycles, obs_every, c->grid, c->block, c->wg_domains, c->stream);
+    if (c->engine != SPKMC_ENGINE_CYCLE) {
+        e = launch_persistent(c->g, c->cycle, ncycles, obs_every, c->grid, c->block, c->wg_domains,
+                              c->engine == SPKMC_ENGINE_INCREMENTAL, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "persistent kernel launch");
         c->cycle += ncycles;
     } else {
@@ -480,14 +489,16 @@ spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *n
         nc.push_back(ncycles[i]);
     }
     if (live.empty()) return SPKMC_OK;
-    const int rows = h == 16 ? 32 : 64;
+    const int rows = persist_rows(h, false), pmax = persist_max_passes(h, false);
     std::vector<int> Ps;
     if (wg_domains) {
-        if (wg_domains % rows || (wg_domains / rows != 1 && wg_domains / rows != 2 && wg_domains / rows != 4))
-            return fail(nullptr, SPKMC_E_INVAL, "wg_domains must be 1, 2 or 4 passes of the row count");
-        Ps.push_back(wg_domains / rows);
+        const int pc = wg_domains / rows;
+        if (wg_domains % rows || pc > pmax || (pc & (pc - 1)))
+            return fail(nullptr, SPKMC_E_INVAL, "wg_domains must be 1, 2 or 4 passes of the row count (at most " +
+                                                    std::to_string(pmax) + " for this octant edge)");
+        Ps.push_back(pc);
     } else {
-        Ps = {1, 2, 4};
+        for (int P = 1; P <= pmax; P <<= 1) Ps.push_back(P);
     }
     std::vector<unsigned char> host(replica_bytes() * live.size());
     Replica *reps = reinterpret_cast<Replica *>(host.data());

@@ -32,7 +32,7 @@ struct alignas(256) DevState {
 };
 static_assert(sizeof(DevState) == 256, "DevState must stay 256 bytes");
 
-enum : uint32_t { kErrBarrierTimeout = 1, kErrFlagTimeout = 2, kErrSelect = 4 };
+enum : uint32_t { kErrBarrierTimeout = 1, kErrFlagTimeout = 2, kErrSelect = 4, kErrHist = 8 };
 
 // Geometry and buffer addresses, passed to every kernel by value.
 struct Geom {
@@ -52,6 +52,7 @@ struct Geom {
     uint32_t *hist;        // K x 16 (14 used)
     uint64_t *flip;        // K flip records
     uint64_t *sync;        // persistent engine: R_max slots, flags, record partials (9 G words)
+    uint64_t *dh;          // PACKED: class changes pushed across workgroups, K x 8 octants x 2 spins
     int8_t *spin8;         // INT8 spins
     uint32_t *A;           // PACKED spins, octant-major, canonical order inside an octant
     uint32_t *F;           // PACKED face copies: per octant x0, x1, y0, y1, z0, z1 (h^2 bits each)

@@ -101,7 +101,7 @@ struct spkmc_server {
     std::vector<hipEvent_t> spare_events;
     DevState *pinned = nullptr;  // max_live * (inflight + 1) headers
     std::vector<int> free_slots;
-    uint32_t cap[2] = {0, 0};  // resident workgroups of the batch kernel, h = 8 and 16, 4 passes
+    uint32_t cap[2] = {0, 0};  // resident workgroups of the batch kernel, h = 8 and 16, most passes
     uint64_t next_id = 1;
     uint64_t n_done = 0, n_failed = 0, n_finishing = 0;
     uint64_t macro_steps = 0, launches = 0, in_use = 0, peak = 0;
@@ -197,8 +197,9 @@ static spkmc_status admit(spkmc_server *s) {
             continue;
         }
         std::string why;
+        const int h = r.ctx->g.h;
         r.batched = persistent_supported(r.ctx->g, r.ctx->p, why) &&
-                    batch_wgs(r.ctx->g, 4) <= s->cap[r.ctx->g.h == 16];
+                    batch_wgs(r.ctx->g, persist_max_passes(h, false)) <= s->cap[h == 16];
         r.state = SPKMC_REQ_RUNNING;
         s->live.push_back(r.id);
     }
@@ -207,14 +208,15 @@ static spkmc_status admit(spkmc_server *s) {
 
 // First fit by decreasing workgroups into launches the device holds at once.
 static std::vector<std::vector<Request *>> pack(std::vector<Request *> rs, uint32_t cap) {
-    std::sort(rs.begin(), rs.end(), [](Request *a, Request *b) {
-        uint32_t wa = batch_wgs(a->ctx->g, 4), wb = batch_wgs(b->ctx->g, 4);
+    auto wgs = [](const Request *r) { return batch_wgs(r->ctx->g, persist_max_passes(r->ctx->g.h, false)); };
+    std::sort(rs.begin(), rs.end(), [&](Request *a, Request *b) {
+        uint32_t wa = wgs(a), wb = wgs(b);
         return wa != wb ? wa > wb : a->id < b->id;
     });
     std::vector<std::vector<Request *>> bins;
     std::vector<uint32_t> used;
     for (Request *r : rs) {
-        uint32_t w = batch_wgs(r->ctx->g, 4);
+        uint32_t w = wgs(r);
         size_t b = 0;
         while (b < bins.size() && used[b] + w > cap) ++b;
         if (b == bins.size()) {
@@ -380,8 +382,8 @@ spkmc_status spkmc_server_create(const spkmc_server_config *cfg, void *dev_pool,
     }
     memset((void *)s->pinned, 0, slots * sizeof(DevState));
     for (size_t i = slots; i-- > 0;) s->free_slots.push_back((int)i);
-    s->cap[0] = batch_capacity(8, 4);
-    s->cap[1] = batch_capacity(16, 4);
+    s->cap[0] = batch_capacity(8, persist_max_passes(8, false));
+    s->cap[1] = batch_capacity(16, persist_max_passes(16, false));
     s->t0 = std::chrono::steady_clock::now();
     *out = s;
     return SPKMC_OK;

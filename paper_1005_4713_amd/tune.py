@@ -22,6 +22,7 @@ import torch
 from . import spkmc
 
 ROWS = {8: 64, 16: 32}
+MAX_PASSES = {8: 4, 16: 4}
 
 
 def domain_choices(L):
@@ -62,10 +63,11 @@ def make_plan(specs, policy, passes, capacity):
         idx = [i for i, d in enumerate(doms) if d // 2 == h]
         if not idx:
             continue
-        P = passes[h]
+        P = min(passes[h], MAX_PASSES[h])
         for b in pack([(i, wgs(specs[i]["L"], doms[i], P)) for i in idx], capacity):
             launches.append({"h": h, "P": P, "wg_domains": ROWS[h] * P, "members": b["members"], "wgs": b["wgs"]})
-    return {"policy": policy, "passes": dict(passes), "domains": doms, "launches": launches}
+    return {"policy": policy, "passes": {h: min(P, MAX_PASSES[h]) for h, P in passes.items()}, "domains": doms,
+            "launches": launches}
 
 
 def build(specs, doms, record_cap=0, device=None):

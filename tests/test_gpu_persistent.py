@@ -1,6 +1,8 @@
-"""GPU parity of the persistent engine (one cooperative launch per spkmc_run):
-against the CPU oracle, against the per-cycle engine, and across launch shapes.
-Bar: spins, fired/null counts, M and B bit-exact; clock within 1e-12 relative.
+"""GPU parity of the persistent engines (one cooperative launch per spkmc_run;
+"persistent" bins the active octant every cycle, "incremental" keeps the class
+histograms of all octants and follows every flip): against the CPU oracle,
+against the per-cycle engine, and across launch shapes.  Bar: spins, fired/null
+counts, M and B bit-exact; clock within 1e-12 relative.
 """
 import numpy as np
 import pytest
@@ -33,6 +35,10 @@ def _orc(L, d, **kw):
     return oracle.Sim(L=L, d=d, **kw)
 
 
+ENGINES = ["persistent", "incremental"]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("L,d,kw", [
     (64, 32, dict()),                                        # h = 16, one workgroup
     (128, 32, dict(rates="metropolis", H=0.05)),             # h = 16, two workgroups
@@ -41,12 +47,12 @@ def _orc(L, d, **kw):
     (64, 16, dict(H=-0.05, T=4.6)),                          # h = 8, one full workgroup
     (128, 16, dict(rates="metropolis", init="down")),        # h = 8, eight workgroups
 ])
-def test_persistent_vs_oracle(spkmc, L, d, kw):
-    print("case", L, d, kw, flush=True)
+def test_persistent_vs_oracle(spkmc, L, d, kw, engine):
+    print("case", engine, L, d, kw, flush=True)
     kw.setdefault("T", 4.5115)
-    gpu = spkmc.Sim(L, d, layout="packed", engine="persistent", seed=5, record_cap=256, **kw)
+    gpu = spkmc.Sim(L, d, layout="packed", engine=engine, seed=5, record_cap=256, **kw)
     info = gpu.info()
-    assert info["engine"] == spkmc.ENGINES["persistent"]
+    assert info["engine"] == spkmc.ENGINES[engine]
     orc = _orc(L, d, seed=5, **kw)
     # launches of different lengths, records every 10 cycles across launch boundaries
     n_done = 0
@@ -62,10 +68,11 @@ def test_persistent_vs_oracle(spkmc, L, d, kw):
         assert np.array_equal(gpu.spins(), orc.spins())
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("L,d", [(256, 32), (256, 16)])
-def test_persistent_equals_cycle_engine(spkmc, L, d):
-    print("case", L, d, flush=True)
-    a = spkmc.Sim(L, d, layout="packed", engine="persistent", seed=9, record_cap=64)
+def test_persistent_equals_cycle_engine(spkmc, L, d, engine):
+    print("case", engine, L, d, flush=True)
+    a = spkmc.Sim(L, d, layout="packed", engine=engine, seed=9, record_cap=64)
     b = spkmc.Sim(L, d, layout="packed", engine="cycle", seed=9, record_cap=64)
     a.run(300, obs_every=25)
     b.run(300, obs_every=25)
@@ -74,15 +81,16 @@ def test_persistent_equals_cycle_engine(spkmc, L, d):
     assert np.array_equal(a.spins(), b.spins())
 
 
-def test_launch_shapes_bit_identical(spkmc):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_launch_shapes_bit_identical(spkmc, engine):
     """Different domains per workgroup (and so different workgroup counts and
     neighbour sets) must give the same trajectory bit for bit."""
     outs = []
     for L, d, shapes in ((256, 32, (32, 64, 128)), (256, 16, (64, 128, 256))):
         ref = None
         for wd in shapes:
-            print("case", L, d, wd, flush=True)
-            s = spkmc.Sim(L, d, layout="packed", engine="persistent", wg_domains=wd, seed=13, record_cap=64)
+            print("case", engine, L, d, wd, flush=True)
+            s = spkmc.Sim(L, d, layout="packed", engine=engine, wg_domains=wd, seed=13, record_cap=64)
             assert s.info()["wg_domains"] == wd
             s.run(120, obs_every=1)
             out = (s.records(), s.state(), s.spins().tobytes())
@@ -93,9 +101,10 @@ def test_launch_shapes_bit_identical(spkmc):
         outs.append(ref)
 
 
-def test_single_cycle_launches(spkmc):
-    a = spkmc.Sim(128, 32, layout="packed", engine="persistent", seed=3, record_cap=64)
-    b = spkmc.Sim(128, 32, layout="packed", engine="persistent", seed=3, record_cap=64)
+@pytest.mark.parametrize("engine", ENGINES)
+def test_single_cycle_launches(spkmc, engine):
+    a = spkmc.Sim(128, 32, layout="packed", engine=engine, seed=3, record_cap=64)
+    b = spkmc.Sim(128, 32, layout="packed", engine=engine, seed=3, record_cap=64)
     for _ in range(30):
         a.run(1, obs_every=3)
     b.run(30, obs_every=3)
@@ -132,3 +141,17 @@ def test_headline_l1024_first_cycles(spkmc):
     for g_, o_ in zip(gpu.records(2), ro):
         _same(g_, o_)
     assert np.array_equal(gpu.spins(), orc.spins())
+
+
+@pytest.mark.parametrize("L,d", [(256, 32), (128, 16)])
+def test_incremental_equals_rebin_long(spkmc, L, d):
+    """Over 1500 cycles in one launch (every octant folded many times, pushed
+    class changes from other workgroups folded at every visit) the incremental
+    engine stays bit-identical to the re-binning one."""
+    print("case long", L, d, flush=True)
+    a = spkmc.Sim(L, d, layout="packed", engine="incremental", seed=21, H=0.05, record_cap=512)
+    b = spkmc.Sim(L, d, layout="packed", engine="persistent", seed=21, H=0.05, record_cap=512)
+    a.run(1500, obs_every=5)
+    b.run(1500, obs_every=5)
+    assert a.records() == b.records()
+    assert np.array_equal(a.spins(), b.spins())
