@@ -68,7 +68,7 @@ def calibrate_copy(mib):
     print(json.dumps({"calibrate_copy_bytes": n, "copies": 3, "read_bytes_per_copy": n, "write_bytes_per_copy": n}))
 
 
-def measured_traffic(workload_name, steps):
+def measured_traffic(workload_name, kernel, steps):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary of this kernel and workload (each scaled by the reading of a plain
     copy of known size); None if there is none or the kernel source changed
@@ -78,7 +78,7 @@ def measured_traffic(workload_name, steps):
     for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")):
         with open(path) as f:
             rec = json.load(f)
-        if rec.get("workload") != workload_name:
+        if rec.get("workload") != workload_name or rec.get("kernel") != kernel:
             continue
         m = hashlib.sha256()
         for name in rec["source_files"]:
@@ -86,6 +86,7 @@ def measured_traffic(workload_name, steps):
                 m.update(f.read())
         if m.hexdigest()[:16] != rec["source_hash"]:
             return None, None
+        rec["path"] = os.path.relpath(path, ROOT)
         return rec["hbm_bytes_per_cycle"] * steps, rec
     return None, None
 
@@ -298,9 +299,12 @@ def main():
     bytes_cycle = info["bytes_per_cycle"]
     launches = 1 if info["engine"] in (spkmc.ENGINES["persistent"], spkmc.ENGINES["incremental"]) else 3 * args.steps
     achieved = bytes_cycle * args.steps / secs / 1e9
+    kernel = (f"k_persistent<{info['h']}, {info['wg_domains'] * 16 // info['block']}, {info['block']}, "
+              f"{str(info['engine'] == spkmc.ENGINES['incremental']).lower()}>" if launches == 1
+              else "whole cycle (3 launches)")
     traffic, traffic_rec = (None, None)
     if launches == 1:
-        traffic, traffic_rec = measured_traffic(w["name"], args.steps)
+        traffic, traffic_rec = measured_traffic(w["name"], kernel, args.steps)
     out = {
         "metric": METRIC,
         "value": value,
@@ -325,13 +329,13 @@ def main():
         "sim_time": [s0[3], s1[3]],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "spkmc_persistent" if launches == 1 else "whole cycle (3 launches)",
+                     "kernel": kernel,
                      "bytes_per_cycle": bytes_cycle, "launches": launches,
                      "avg_launch_ms": gpu_ms / launches,
-                     "traffic_source": None if traffic is None else "profiles/persistent_L1024_d32_traffic.json"},
+                     "traffic_source": None if traffic is None else traffic_rec["path"]},
     }
     if not args.no_cpu_baseline:
-        cyc = args.cpu_cycles or (3 if w["L"] >= 1024 else 20 if w["L"] >= 512 else 2000)
+        cyc = args.cpu_cycles or (12 if w["L"] >= 1024 else 80 if w["L"] >= 512 else 4000)
         print(f"bench: cpu baseline, {cyc} oracle cycles", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, cyc)
     print(json.dumps(out), flush=True)

@@ -147,9 +147,11 @@ __device__ __forceinline__ int wrapp(int v, int nd) { return v + 1 == nd ? 0 : v
 // above (x0/y0/z0 face).  nb holds the six neighbour domains of k
 // (-x, +x, -y, +y, -z, +z).
 struct HaloFaces {
-    const uint32_t *lo[3];  // face at local coordinate h - 1 of the octant below
-    const uint32_t *hi[3];  // face at local coordinate 0 of the octant above
+    uint32_t lo[3];  // word index in F of the face at local coordinate h - 1 of the octant below
+    uint32_t hi[3];  // word index in F of the face at local coordinate 0 of the octant above
 };
+// (32-bit word indices from the uniform base: F holds K * 48 h^2 / 32 words,
+// below 2^31 for every supported size)
 __device__ __forceinline__ HaloFaces halo_faces(const Geom &g, uint32_t k, int s, const uint32_t *nb) {
     HaloFaces hf;
     const uint32_t fw = g.h2 / 32;  // words per face
@@ -158,8 +160,8 @@ __device__ __forceinline__ HaloFaces halo_faces(const Geom &g, uint32_t k, int s
         const int bit = (s >> a) & 1;
         const uint32_t c = (uint32_t)(s ^ (1 << a));
         const uint32_t kmi = bit ? k : nb[2 * a], kpi = bit ? nb[2 * a + 1] : k;  // below / above
-        hf.lo[a] = g.F + ((uint64_t)kmi * 8 + c) * g.fwpo + (2 * a + 1) * fw;
-        hf.hi[a] = g.F + ((uint64_t)kpi * 8 + c) * g.fwpo + (2 * a) * fw;
+        hf.lo[a] = (kmi * 8u + c) * g.fwpo + (uint32_t)(2 * a + 1) * fw;
+        hf.hi[a] = (kpi * 8u + c) * g.fwpo + (uint32_t)(2 * a) * fw;
     }
     return hf;
 }
@@ -256,21 +258,21 @@ __device__ __forceinline__ void load16(const Geom &g, uint32_t k, int s, bool va
     for (int p = 0; p < 8; ++p) r.W[p] = 0;
     r.xm = r.xp = r.ym = r.yp = r.zw = 0;
     if (!valid) return;
-    const uint32_t *A = g.A + ((uint64_t)k * 8 + s) * 128 + l * 8;
+    const uint32_t a0 = (k * 8u + (uint32_t)s) * 128u + (uint32_t)l * 8u;  // word index, < N / 32
 #pragma unroll
     for (int p = 0; p < 8; p += 2) {
-        uint64_t v = ld_words2(A + p);
+        uint64_t v = ld_words2(&g.A[a0 + p]);
         r.W[p] = (uint32_t)v;
         r.W[p + 1] = (uint32_t)(v >> 32);
     }
     HaloFaces hf = halo_faces(g, k, s, nb);
     // x faces: bit ly + 16 lz -> half-word l; y faces: bit lx + 16 lz -> half-word l
-    r.xm = ld32(hf.lo[0] + (l >> 1));
-    r.xp = ld32(hf.hi[0] + (l >> 1));
-    r.ym = ld32(hf.lo[1] + (l >> 1));
-    r.yp = ld32(hf.hi[1] + (l >> 1));
+    r.xm = ld32(&g.F[hf.lo[0] + (l >> 1)]);
+    r.xp = ld32(&g.F[hf.hi[0] + (l >> 1)]);
+    r.ym = ld32(&g.F[hf.lo[1] + (l >> 1)]);
+    r.yp = ld32(&g.F[hf.hi[1] + (l >> 1)]);
     // z faces (bit lx + 16 ly, the layout of a plane), one word per lane
-    r.zw = ld32((l < 8 ? hf.lo[2] : hf.hi[2]) + (l & 7));
+    r.zw = ld32(&g.F[(l < 8 ? hf.lo[2] : hf.hi[2]) + (l & 7)]);
 }
 
 // zrow: this row's 24 LDS words: face below (8), face above (8), zeros (8).
@@ -301,7 +303,7 @@ __device__ __forceinline__ void compute16(const Raw<16> &r, bool valid, int l, u
         P.b0[p] = o0;
         P.b1[p] = o1;
         P.b2[p] = o2;
-        if (MOM && valid) moments(w, o0, o1, o2, m);
+        if (MOM) moments(w, o0, o1, o2, m);  // invalid rows hold zeros
     }
 }
 
@@ -314,17 +316,17 @@ __device__ __forceinline__ void load8(const Geom &g, uint32_t k, int s, bool val
     int lz = l >> 1, p = l & 1;
     r.w = r.xm = r.xp = r.yface = r.zface = 0;
     if (!valid) return;
-    r.w = ld32(g.A + ((uint64_t)k * 8 + s) * 16 + l);
+    r.w = ld32(&g.A[(k * 8u + (uint32_t)s) * 16u + (uint32_t)l]);
     HaloFaces hf = halo_faces(g, k, s, nb);
     // x faces: bit ly + 8 lz; rows 4p..4p+3 of plane lz = bits 4l .. 4l + 3
-    r.xm = ld32(hf.lo[0] + (l >> 3));
-    r.xp = ld32(hf.hi[0] + (l >> 3));
+    r.xm = ld32(&g.F[hf.lo[0] + (l >> 3)]);
+    r.xp = ld32(&g.F[hf.hi[0] + (l >> 3)]);
     // y faces: bit lx + 8 lz = byte lz; the lowest row of p = 0 needs the face below,
     // the highest row of p = 1 the face above
-    r.yface = ld32((p == 0 ? hf.lo[1] : hf.hi[1]) + (lz >> 2));
+    r.yface = ld32(&g.F[(p == 0 ? hf.lo[1] : hf.hi[1]) + (lz >> 2)]);
     // z faces: bit lx + 8 ly, word p covers rows 4p .. 4p + 3
-    if (lz == 0) r.zface = ld32(hf.lo[2] + p);
-    if (lz == 7) r.zface = ld32(hf.hi[2] + p);
+    if (lz == 0) r.zface = ld32(&g.F[hf.lo[2] + p]);
+    if (lz == 7) r.zface = ld32(&g.F[hf.hi[2] + p]);
 }
 template <bool MOM>
 __device__ __forceinline__ void compute8(const Raw<8> &r, bool valid, int l, uint32_t *, Planes<8> &P,
@@ -347,7 +349,7 @@ __device__ __forceinline__ void compute8(const Raw<8> &r, bool valid, int l, uin
     P.b0[0] = o0;
     P.b1[0] = o1;
     P.b2[0] = o2;
-    if (MOM && valid) moments(w, o0, o1, o2, m);
+    if (MOM) moments(w, o0, o1, o2, m);  // invalid rows hold zeros
 }
 
 template <int H>
@@ -706,21 +708,22 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             __syncthreads();
         } else {
             // --- steps 1 and 4a: class planes and moments of the active octants
-            Raw<H> raw[2];
-            load_octant<H>(g, kbase + (uint32_t)row, s, (uint32_t)row < nvalid, l, sh.nbdom[row], raw[0]);
+            // (the words of every pass in flight at once; each pass's raw words
+            // give way to its planes)
+            Raw<H> raw[P];
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                const uint32_t ld = (uint32_t)(pp * rows + row);
+                load_octant<H>(g, kbase + ld, s, ld < nvalid, l, sh.nbdom[ld < nvalid ? ld : 0], raw[pp]);
+            }
 #pragma unroll
             for (int pp = 0; pp < P; ++pp) {
                 uint32_t ld = (uint32_t)(pp * rows + row);
                 bool valid = ld < nvalid;
-                if (pp + 1 < P) {  // next pass's words in flight while this pass computes
-                    uint32_t ldn = ld + (uint32_t)rows;
-                    load_octant<H>(g, kbase + ldn, s, ldn < nvalid, l, sh.nbdom[ldn < nvalid ? ldn : 0],
-                                   raw[(pp + 1) & 1]);
-                }
                 uint32_t m[13];
 #pragma unroll
                 for (int i = 0; i < 13; ++i) m[i] = 0;
-                compute_octant<H, true>(raw[pp & 1], valid, l, sh.zbuf[row], pl[pp], m);
+                compute_octant<H, true>(raw[pp], valid, l, sh.zbuf[row], pl[pp], m);
 #pragma unroll
                 for (int i = 0; i < 13; ++i) m[i] = row_scan(m[i]);
                 if (l == 15) {
