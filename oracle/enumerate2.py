@@ -76,3 +76,62 @@ def averages(J, H, T, rates=0):
         out[name] = {"E": float(p @ E), "absM": float(p @ np.abs(M)), "M2": float(p @ M ** 2),
                      "p": p}
     return out
+
+
+def cycle_law(J, H, T, rates=0, colours=8, scope=0):
+    """Exact time-weighted stationary law of the spkMC cycle on the periodic
+    2x2x2 lattice with domain edge 2 (one domain, eight single-site octants).
+
+    A cycle draws a colour uniformly: one site (8 colours) or the four sites of
+    one parity of x + y + z (2 colours, never neighbours of one another).  Every
+    active site fires independently with probability r_s / R, where R is the
+    largest rate among the active sites (scope 0), among all eight sites
+    (scope 1), or the largest rate any site can have (scope 2: the largest
+    single-flip rate over every state of the lattice).  The cycle lasts
+    Exp(1) / (S R) with S the number of colours.  The jump chain's stationary
+    law, weighted by the mean cycle length in each state, is the law of the
+    state at a random time."""
+    beta = 1.0 / T
+    E = np.zeros(256)
+    rate = np.zeros((256, 8))
+    for st in range(256):
+        sp = spins_of(st)
+        e0, _, _ = energy(sp, J, H)
+        E[st] = e0
+        for s in range(8):
+            sp2 = sp.copy()
+            sp2[s] = -sp2[s]
+            e1, _, _ = energy(sp2, J, H)
+            rate[st, s] = flip_rate(e1 - e0, beta, rates)
+    rbound = rate.max()
+    if colours == 8:
+        groups = [[s] for s in range(8)]
+    else:
+        groups = [[s for s in range(8) if bin(s).count("1") % 2 == c] for c in (0, 1)]
+    P = np.zeros((256, 256))
+    hold = np.zeros(256)
+    for st in range(256):
+        for grp in groups:
+            if scope == 0:
+                R = max(rate[st, s] for s in grp)
+            elif scope == 1:
+                R = rate[st].max()
+            else:
+                R = rbound
+            hold[st] += (1.0 / len(groups)) / (colours * R)
+            probs = [rate[st, s] / R for s in grp]
+            for mask in range(1 << len(grp)):
+                pr = 1.0
+                nxt = st
+                for b, s in enumerate(grp):
+                    if (mask >> b) & 1:
+                        pr *= probs[b]
+                        nxt ^= 1 << s
+                    else:
+                        pr *= 1.0 - probs[b]
+                P[st, nxt] += pr / len(groups)
+    w, v = np.linalg.eig(P.T)
+    pi = np.real(v[:, np.argmin(np.abs(w - 1.0))])
+    pi = pi / pi.sum()
+    pt = pi * hold
+    return pt / pt.sum()

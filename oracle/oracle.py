@@ -49,6 +49,7 @@ def _load():
         "orc_sim_check_failures": (C.c_uint64, [vp]),
         "orc_sim_get_spins": (None, [vp, i8p]),
         "orc_sim_rate": (C.c_double, [vp, C.c_int]),
+        "orc_sim_rbound": (C.c_double, [vp]),
         "orc_sim_set_state": (C.c_int, [vp, i8p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_double]),
         "orc_sim_octant_hist": (None, [vp, C.c_uint32, C.c_int32, u32p]),
         "orc_sim_run_grid": (C.c_uint64, [vp, f64p, C.c_uint64, i64p, i64p, C.c_uint64]),
@@ -191,6 +192,9 @@ class Sim:
 
     def rates(self):
         return np.array([lib.orc_sim_rate(self.h, c) for c in range(14)])
+
+    def rbound(self):
+        return lib.orc_sim_rbound(self.h)
 
     def run_grid(self, grid, max_cycles=1 << 62):
         grid = np.ascontiguousarray(grid, dtype=np.float64)

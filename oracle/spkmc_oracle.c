@@ -48,6 +48,16 @@
  *       independent parallel streams).
  *   R8  neighbours are counted with multiplicity (at L = 2 the +x and -x
  *       neighbour coincide and count twice).
+ *   R9  two colours (Sec. 3.2, first-neighbour interactions): the cells of
+ *       edge h (the octants) coloured by the parity of sx + sy + sz, a proper
+ *       two-colouring of the cell lattice, so same-coloured cells never share
+ *       a face; each cycle activates the 4 octants of the drawn colour in
+ *       every domain, each octant its own frequency line (subdomain) with its
+ *       own random stream; the colour is the top bit of the cycle word.
+ *  R10  the optimistic bound R'_max of Sec. 3.2 (printed with a garbled
+ *       exponent): the largest aggregate rate a region of n_k sites can have,
+ *       n_k times the largest of the 14 class rates; fixed for the whole run,
+ *       so no maximum over subdomains is taken.
  */
 #include <math.h>
 #include <stdint.h>
@@ -115,8 +125,10 @@ typedef struct {
     uint64_t seed;      /* Philox key                                               */
     int32_t rates;      /* 0 Glauber (eq. 3, reading R1), 1 Metropolis              */
     int32_t init;       /* 0 iid +-1 from the seed, 1 all +1, 2 all -1              */
-    int32_t colours;    /* 8 = octant chessboard; 1 = the whole domain is active    */
-    int32_t rmax_scope; /* 0 = max over active octants (R4), 1 = over all octants   */
+    int32_t colours;    /* 8 = octant chessboard; 2 = octant parity (R9); 1 = the
+                           whole domain is active                                   */
+    int32_t rmax_scope; /* 0 = max over active lines (R4), 1 = over all octants,
+                           2 = the optimistic bound R'_max (R10)                    */
     int32_t order;      /* 0 decide all then apply, 1 apply at once in domain order,
                            2 apply at once in a shuffled domain order               */
     int32_t check;      /* 1 = recompute M and B after every cycle                  */
@@ -264,8 +276,10 @@ typedef struct {
     uint32_t K;
     double r[14];
     lattice g;
-    uint32_t *hist; /* K * 14, active octants of the current cycle */
-    double *R;      /* K */
+    uint32_t A;     /* active lines (octants) per domain and cycle: 1, or 4 (R9) */
+    double Rbound;  /* R'_max (R10) */
+    uint32_t *hist; /* K * A * 14, active lines of the current cycle */
+    double *R;      /* K * A */
     uint64_t n, fired, nulls;
     double t;
     int64_t M, B;
@@ -282,7 +296,7 @@ static void region(const orc_sim *S, uint32_t k, int s, int *ox, int *oy, int *o
     int nd = S->nd;
     int kx = (int)(k % (uint32_t)nd), ky = (int)((k / (uint32_t)nd) % (uint32_t)nd),
         kz = (int)(k / ((uint32_t)nd * (uint32_t)nd));
-    if (S->S == 8) {
+    if (S->S != 1) {
         *ox = kx * S->d + (s & 1) * S->h;
         *oy = ky * S->d + ((s >> 1) & 1) * S->h;
         *oz = kz * S->d + ((s >> 2) & 1) * S->h;
@@ -328,9 +342,9 @@ static int64_t find_site(const orc_sim *S, uint32_t k, int s, int c, uint32_t j,
 ORC_EXPORT orc_sim *orc_sim_new(const orc_params *p) {
     if (!p) return NULL;
     if (p->L < 2 || p->d < 2 || (p->d & 1) || p->L % p->d) return NULL;
-    if (p->colours != 8 && p->colours != 1) return NULL;
+    if (p->colours != 8 && p->colours != 2 && p->colours != 1) return NULL;
     if (p->colours == 1 && p->d != p->L) return NULL; /* one region only: K must be 1 */
-    if (p->init < 0 || p->init > 2 || p->rmax_scope < 0 || p->rmax_scope > 1) return NULL;
+    if (p->init < 0 || p->init > 2 || p->rmax_scope < 0 || p->rmax_scope > 2) return NULL;
     if (p->order < 0 || p->order > 2) return NULL;
     orc_sim *S = (orc_sim *)calloc(1, sizeof(orc_sim));
     if (!S) return NULL;
@@ -342,18 +356,27 @@ ORC_EXPORT orc_sim *orc_sim_new(const orc_params *p) {
     S->S = p->colours;
     S->N = (int64_t)p->L * p->L * p->L;
     S->K = (uint32_t)S->nd * (uint32_t)S->nd * (uint32_t)S->nd;
+    S->A = p->colours == 2 ? 4u : 1u;
     if (orc_rate_table(p->J, p->H, p->T, p->rates, S->r) != 0) {
         free(S);
         return NULL;
     }
+    {   /* R10: sites of one region times the largest class rate */
+        double rb = S->r[0];
+        for (int c = 1; c < 14; ++c)
+            if (S->r[c] > rb) rb = S->r[c];
+        int e = p->colours == 1 ? S->d : S->h;
+        S->Rbound = (double)((int64_t)e * e * e) * rb;
+    }
+    const size_t nl = (size_t)S->K * S->A;
     S->g.L = p->L;
     S->g.spin = (int8_t *)malloc((size_t)S->N);
-    S->hist = (uint32_t *)calloc((size_t)S->K * 14, sizeof(uint32_t));
-    S->R = (double *)calloc(S->K, sizeof(double));
-    S->flip_site = (int64_t *)malloc(sizeof(int64_t) * S->K);
-    S->flip_old = (int8_t *)malloc(S->K);
-    S->flip_a = (int8_t *)malloc(S->K);
-    S->perm = (uint32_t *)malloc(sizeof(uint32_t) * S->K);
+    S->hist = (uint32_t *)calloc(nl * 14, sizeof(uint32_t));
+    S->R = (double *)calloc(nl, sizeof(double));
+    S->flip_site = (int64_t *)malloc(sizeof(int64_t) * nl);
+    S->flip_old = (int8_t *)malloc(nl);
+    S->flip_a = (int8_t *)malloc(nl);
+    S->perm = (uint32_t *)malloc(sizeof(uint32_t) * nl);
     if (!S->g.spin || !S->hist || !S->R || !S->flip_site || !S->flip_old || !S->flip_a || !S->perm) {
         free(S->g.spin); free(S->hist); free(S->R); free(S->flip_site);
         free(S->flip_old); free(S->flip_a); free(S->perm); free(S);
@@ -377,6 +400,19 @@ static void flip_apply(orc_sim *S, int64_t site, int8_t old, int a) {
     S->B += 12 - 4 * (int64_t)a;
 }
 
+/* octant of the a-th active line for the drawn colour (R3 / R9) */
+static int line_octant(const orc_sim *S, int colour, uint32_t a) {
+    if (S->S != 2) return colour;
+    uint32_t seen = 0;
+    for (int s = 0; s < 8; ++s) {
+        int parity = (s & 1) ^ ((s >> 1) & 1) ^ ((s >> 2) & 1);
+        if (parity != colour) continue;
+        if (seen == a) return s;
+        ++seen;
+    }
+    return -1;
+}
+
 /* One spkMC cycle n (steps 1-6 with 4a/4b).  Returns the cycle increment dt. */
 static double spkmc_cycle(orc_sim *S) {
     uint64_t n = S->n;
@@ -384,36 +420,44 @@ static double spkmc_cycle(orc_sim *S) {
     uint32_t gw[4];
     /* step 4a and the step-5 draw: one stream shared by all domains */
     philox_words(S->p.seed, nlo, nhi, 0xFFFFFFFFu, 0xFFFFFFFFu, gw);
-    int s = (S->S == 8) ? (int)(gw[0] >> 29) : 0;
+    int colour = (S->S == 8) ? (int)(gw[0] >> 29) : (S->S == 2) ? (int)(gw[0] >> 31) : 0;
     double ut = orc_uopen52(gw[2], gw[3]);
+    const uint32_t nl = S->K * S->A; /* frequency lines (subdomains) of this cycle */
 
-    /* step 1: frequency line of every active octant */
-    for (uint32_t k = 0; k < S->K; ++k) {
-        bin_region(S, k, s, &S->hist[(size_t)k * 14]);
-        S->R[k] = line_total(&S->hist[(size_t)k * 14], S->r);
+    /* step 1: frequency line of every active region (line f = A k + a) */
+    for (uint32_t f = 0; f < nl; ++f) {
+        uint32_t k = f / S->A;
+        int s = line_octant(S, colour, f % S->A);
+        bin_region(S, k, s, &S->hist[(size_t)f * 14]);
+        S->R[f] = line_total(&S->hist[(size_t)f * 14], S->r);
     }
-    /* step 2: R_max (reading R4; scope 1 takes every octant of every colour) */
+    /* step 2: R_max (reading R4; scope 1 takes every octant of every colour;
+     * scope 2 the fixed bound of R10) */
     double Rmax = 0.0;
     if (S->p.rmax_scope == 0) {
-        for (uint32_t k = 0; k < S->K; ++k)
-            if (S->R[k] > Rmax) Rmax = S->R[k];
-    } else {
+        for (uint32_t f = 0; f < nl; ++f)
+            if (S->R[f] > Rmax) Rmax = S->R[f];
+    } else if (S->p.rmax_scope == 1) {
         uint32_t h2[14];
         for (uint32_t k = 0; k < S->K; ++k)
-            for (int c = 0; c < S->S; ++c) {
+            for (int c = 0; c < (S->S == 1 ? 1 : 8); ++c) {
                 bin_region(S, k, c, h2);
                 double Rc = line_total(h2, S->r);
                 if (Rc > Rmax) Rmax = Rc;
             }
+    } else {
+        Rmax = S->Rbound;
+        for (uint32_t f = 0; f < nl; ++f)
+            if (S->R[f] > Rmax) S->check_fail++; /* cannot happen: R'_max bounds every line */
     }
 
-    /* steps 3, 4, 4b: in every domain an event with probability r / R_max */
+    /* steps 3, 4, 4b: in every line an event with probability r / R_max */
     uint32_t nfire = 0;
-    for (uint32_t k = 0; k < S->K; ++k) S->perm[k] = k;
+    for (uint32_t f = 0; f < nl; ++f) S->perm[f] = f;
     if (S->p.order == 2) {
         /* shuffled order: any permutation must give the same result */
         uint64_t st = 0x9E3779B97F4A7C15ull ^ n;
-        for (uint32_t i = S->K; i > 1; --i) {
+        for (uint32_t i = nl; i > 1; --i) {
             st = st * 6364136223846793005ull + 1442695040888963407ull;
             uint32_t jx = (uint32_t)((st >> 33) % i);
             uint32_t tmp = S->perm[i - 1];
@@ -421,17 +465,19 @@ static double spkmc_cycle(orc_sim *S) {
             S->perm[jx] = tmp;
         }
     }
-    for (uint32_t ii = 0; ii < S->K; ++ii) {
-        uint32_t k = S->perm[ii];
+    for (uint32_t ii = 0; ii < nl; ++ii) {
+        uint32_t f = S->perm[ii];
+        uint32_t k = f / S->A;
+        int s = line_octant(S, colour, f % S->A);
         uint32_t dw[4];
         philox_words(S->p.seed, nlo, nhi, k, (uint32_t)s, dw);
         double u = orc_u53(dw[0], dw[1]);
         int32_t c;
         uint32_t j;
-        const uint32_t *hk = &S->hist[(size_t)k * 14];
+        const uint32_t *hk = &S->hist[(size_t)f * 14];
         if (S->p.order != 0) {
             /* flips already applied in this cycle must not have changed this
-             * octant or its halo: recompute and compare */
+             * region or its halo: recompute and compare */
             uint32_t again[14];
             bin_region(S, k, s, again);
             if (memcmp(again, hk, sizeof(again)) != 0) S->check_fail++;
@@ -459,7 +505,7 @@ static double spkmc_cycle(orc_sim *S) {
     double dt = -log(ut) / ((double)S->S * Rmax);
     S->t = S->t + dt;
     S->fired += nfire;
-    S->nulls += (uint64_t)S->K - nfire;
+    S->nulls += (uint64_t)nl - nfire;
     S->n = n + 1;
     if (S->p.check) {
         int64_t M, B;
@@ -498,6 +544,7 @@ ORC_EXPORT void orc_sim_state(const orc_sim *S, orc_record *out) { fill_record(S
 ORC_EXPORT uint64_t orc_sim_check_failures(const orc_sim *S) { return S->check_fail; }
 ORC_EXPORT void orc_sim_get_spins(const orc_sim *S, int8_t *out) { memcpy(out, S->g.spin, (size_t)S->N); }
 ORC_EXPORT double orc_sim_rate(const orc_sim *S, int c) { return S->r[c]; }
+ORC_EXPORT double orc_sim_rbound(const orc_sim *S) { return S->Rbound; }
 
 /* Replace the spins (values must be +-1) and recompute M, B; counters and the
  * clock are set from the arguments (a resumed state). */

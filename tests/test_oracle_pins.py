@@ -259,6 +259,36 @@ def test_order_independence():
         assert outs[0] == outs[1] == outs[2]
 
 
+@pytest.mark.parametrize("scope", [0, 1, 2])
+def test_two_colour_lines_independent(scope):
+    """Two colours: the four active octants of a domain (and of every domain)
+    never touch, so applying each flip at once, in domain order or shuffled,
+    gives the trajectory of deciding every line first; every line's histogram
+    is recomputed before its decision and must be unchanged."""
+    for L, d in [(16, 4), (12, 6), (8, 2)]:
+        outs = []
+        for order in (0, 1, 2):
+            sim = oracle.Sim(L=L, d=d, seed=7, order=order, colours=2, rmax_scope=scope, check=1)
+            recs = sim.run(150, obs_every=10)
+            outs.append((recs, sim.spins().tobytes()))
+            assert sim.check_failures() == 0
+        assert outs[0] == outs[1] == outs[2]
+        K = (L // d) ** 3
+        for (n, fired, nulls, t, M, B) in outs[0][0]:
+            assert fired + nulls == 4 * K * n  # four lines per domain and cycle
+
+
+def test_bound_lowers_utilisation_not_the_law():
+    """R'_max >= R_max: the same trajectory law with more null events; the mean
+    cycle length is 1 / (8 R'_max) exactly."""
+    a = oracle.Sim(L=16, d=8, seed=9, rmax_scope=0)
+    b = oracle.Sim(L=16, d=8, seed=9, rmax_scope=2)
+    ra, rb = a.run(400), b.run(400)
+    sa, sb = a.state(), b.state()
+    assert sb[1] / (sb[1] + sb[2]) < sa[1] / (sa[1] + sa[2])
+    assert abs(sb[3] - 400 / (8 * b.rbound())) < 0.15 * 400 / (8 * b.rbound())
+
+
 def test_resume_is_exact():
     a = oracle.Sim(L=16, d=8, seed=21)
     a.run(300)
@@ -313,6 +343,7 @@ def test_bkl_list_mode_counts_consistent():
 
 
 def test_invalid_geometry_rejected():
-    for kw in [dict(L=16, d=3), dict(L=16, d=6), dict(L=1, d=2), dict(L=16, d=0), dict(L=8, d=4, colours=1)]:
+    for kw in [dict(L=16, d=3), dict(L=16, d=6), dict(L=1, d=2), dict(L=16, d=0), dict(L=8, d=4, colours=1),
+               dict(L=8, d=4, colours=3), dict(L=8, d=4, rmax_scope=3)]:
         with pytest.raises(ValueError):
             oracle.Sim(**kw)

@@ -133,3 +133,47 @@ def test_spkmc_bias_within_serial_deviation():
     ms, ss = integ(lambda r: oracle.Bkl(L=L, T=TC, init=1, seed=2000 + r))
     sigma_b = math.sqrt(sp ** 2 + ss ** 2)
     assert abs(mp - ms) < 3 * sigma_b, (mp, ms, sigma_b)
+
+
+# --- the paper-literal variants: two colours (octant parity) and the optimistic
+# bound R'_max; exact laws from the 256-state transition matrix built from eq. 1
+
+def test_cycle_law_solver_matches_closed_forms():
+    """The matrix solver reproduces the two closed forms it generalises."""
+    T, H = TC, 0.1
+    laws = enumerate2.averages(1.0, H, T, 0)
+    assert np.abs(enumerate2.cycle_law(1.0, H, T, 0, 8, 0) - laws["spkmc_active"]["p"]).max() < 1e-10
+    assert np.abs(enumerate2.cycle_law(1.0, H, T, 0, 8, 1) - laws["boltzmann"]["p"]).max() < 1e-10
+    # the bound is exact uniformisation: Boltzmann for both colourings
+    assert np.abs(enumerate2.cycle_law(1.0, H, T, 0, 8, 2) - laws["boltzmann"]["p"]).max() < 1e-10
+    assert np.abs(enumerate2.cycle_law(1.0, H, T, 0, 2, 2) - laws["boltzmann"]["p"]).max() < 1e-10
+    # two colours with a state-dependent R_max is a different law
+    p2 = enumerate2.cycle_law(1.0, H, T, 0, 2, 0)
+    assert 0.5 * np.abs(p2 - laws["boltzmann"]["p"]).sum() > 0.05
+
+
+@pytest.mark.parametrize("colours,scope", [(2, 0), (2, 1), (2, 2), (8, 2)])
+def test_l2_variant_state_distribution(colours, scope):
+    T, H = TC, 0.1
+    law = enumerate2.cycle_law(1.0, H, T, 0, colours, scope)
+    sim = oracle.Sim(L=2, d=2, T=T, H=H, seed=41 + scope, colours=colours, rmax_scope=scope)
+    _, hist = sim.run_tw(2000000, state_hist=True)
+    p = hist / hist.sum()
+    tv = 0.5 * np.abs(p - law).sum()
+    assert tv < 0.01, (colours, scope, tv)
+    assert sim.check_failures() == 0
+
+
+def test_bound_is_the_largest_line_rate():
+    """R'_max = n_k max_c r_c: reached by a region whose every site is in the
+    fastest class, never exceeded by any line during a run."""
+    for rates, H in ((0, 0.0), (0, 0.3), (1, 0.0)):
+        sim = oracle.Sim(L=16, d=8, T=TC, H=H, rates=rates, seed=3, rmax_scope=2, check=1)
+        r = sim.rates()
+        assert sim.rbound() == 64 * r.max()
+        # class 0 (a down spin whose six neighbours are up) is the fastest
+        # Glauber class for H >= 0
+        if rates == 0:
+            assert r.argmax() == 0
+        sim.run(300)
+        assert sim.check_failures() == 0
