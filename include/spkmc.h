@@ -91,6 +91,22 @@ enum { SPKMC_LAYOUT_INT8 = 0, SPKMC_LAYOUT_PACKED = 1 };
  * All engines produce bit-identical trajectories. */
 enum { SPKMC_ENGINE_AUTO = 0, SPKMC_ENGINE_CYCLE = 1, SPKMC_ENGINE_PERSISTENT = 2, SPKMC_ENGINE_INCREMENTAL = 3 };
 
+/* Method variants (bit flags).
+ * RMAX_ALL (Sec. 3.1 step 2 read literally): R_max is the maximum over every
+ *   octant of every colour, not only the active ones.
+ * TWO_COLOURS (Sec. 3.2, first-neighbour interactions): the octants are
+ *   coloured by the parity of sx + sy + sz; a cycle activates the four octants
+ *   of the drawn colour in every domain, each its own frequency line with its
+ *   own random stream (counter (n, domain, octant)); the colour is the top bit
+ *   of the cycle word and the clock step uses S = 2.
+ * RMAX_BOUND (Sec. 3.2, the optimistic alternative): R_max is the fixed bound
+ *   R'_max = n_k max_c r_c (n_k sites per line), so no maximum over lines is
+ *   taken; more null events, the same dynamics.
+ * RMAX_ALL and RMAX_BOUND exclude each other.  Engines: CYCLE runs every
+ * variant; PERSISTENT runs 0 and RMAX_BOUND; INCREMENTAL runs 0 and RMAX_ALL
+ * (AUTO picks accordingly). */
+enum { SPKMC_VARIANT_RMAX_ALL = 1, SPKMC_VARIANT_TWO_COLOURS = 2, SPKMC_VARIANT_RMAX_BOUND = 4 };
+
 typedef struct spkmc_params {
     uint32_t struct_size; /* sizeof(spkmc_params): ABI check                           */
     int32_t L;            /* lattice edge, >= 2                                        */
@@ -106,7 +122,8 @@ typedef struct spkmc_params {
     int32_t wg_domains;   /* PERSISTENT: domains per workgroup, 0 = default; other
                              values change the launch shape, never the results      */
     uint32_t record_cap;  /* observation records kept on the device (ring)             */
-    uint32_t reserved;    /* must be 0                                                 */
+    uint32_t variant;     /* SPKMC_VARIANT_* bits; 0 = 8 colours, R_max over the K
+                             active octants                                          */
 } spkmc_params;
 
 /* One observation: the state after `cycle` cycles. */
@@ -147,7 +164,8 @@ size_t spkmc_state_bytes(const spkmc_params *p);
  * *out receives the context (also on some errors, so spkmc_last_error can be
  * read; destroy it either way).
  * Errors: E_INVAL (bad parameters: d odd, d < 2, L % d != 0, T <= 0, a rate
- * that is 0 or not finite, unknown enum, wrong struct_size, reserved != 0,
+ * that is 0 or not finite, unknown enum, wrong struct_size, unknown variant
+ * bits or RMAX_ALL with RMAX_BOUND,
  * PACKED with h % 4 != 0), E_RANGE (dev_bytes too small), E_UNSUPPORTED
  * (engine PERSISTENT with parameters it cannot run), E_DEVICE. */
 spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, void *hip_stream,

@@ -10,7 +10,7 @@ hipError_t launch_init(const Geom &g, int init, hipStream_t stream);
 hipError_t launch_faces(const Geom &g, hipStream_t stream);
 hipError_t launch_observables(const Geom &g, hipStream_t stream);
 hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream_t stream);
-bool persistent_supported(const Geom &g, const spkmc_params &p, std::string &why);
+bool persistent_supported(const Geom &g, const spkmc_params &p, bool inc, std::string &why);
 hipError_t persistent_configure(const Geom &g, const spkmc_params &p, bool inc, int &grid, int &block,
                                 int &wg_domains);
 hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid,

@@ -2,9 +2,10 @@
 // kernels of the gfx950 spkMC library.
 //
 // One cycle (Sec. 3.1 steps 1-6, Sec. 3.2 steps 4a/4b) is three launches:
-//   k_bin      one workgroup per domain: class histogram of the active octant
-//              (step 1), its FP64 frequency line R_k, device-wide max (step 2);
-//   k_select   one wavefront per domain: draw, frequency-line walk with the
+//   k_bin      one workgroup per frequency line (an active octant): class
+//              histogram (step 1), its FP64 frequency line R_k, device-wide
+//              max (step 2);
+//   k_select   one wavefront per frequency line: draw, frequency-line walk with the
 //              null event last (steps 3, 4, 4b), canonical-order prefix select
 //              of the site with wavefront ballots, flip (step 6 is the kernel
 //              boundary);
@@ -115,29 +116,69 @@ __global__ void k_observables(Geom g) {
 }
 
 // --------------------------------------------------------------------------- cycle
-// Step 1 and the device-wide max of step 2.  One workgroup per domain.
+// Frequency line f of a cycle: domain f / lpd, octant = the colour (eight
+// colours) or the (f mod 4)-th octant of the colour's parity (two colours).
+__device__ __forceinline__ void line_of(const Geom &g, uint32_t f, int colour, uint32_t &k, int &s) {
+    if (g.lpd == 1) {
+        k = f;
+        s = colour;
+    } else {
+        k = f >> 2;
+        s = two_colour_octant(colour, f & 3u);
+    }
+}
+
+template <class S>
+__device__ __forceinline__ void bin_octant(const Geom &g, uint32_t k, int s, uint32_t *cnt) {
+    int ox, oy, oz;
+    octant_origin(g, k, s, ox, oy, oz);
+    for (uint32_t q = threadIdx.x; q < g.h3; q += blockDim.x) {
+        int x = ox + (int)(q % g.h), y = oy + (int)((q / g.h) % g.h), z = oz + (int)(q / g.h2);
+        int sp = S::get(g, x, y, z);
+        int c = (sp > 0 ? 7 : 0) + aligned_count<S>(g, x, y, z, sp);
+        atomicAdd(&cnt[c], 1u);
+    }
+}
+
+// Step 1 and the device-wide max of step 2.  One workgroup per frequency line.
+// RMAX_ALL: the workgroup also bins the inactive octants it stands for (the
+// other seven with eight colours, octant s ^ 1 with two) into the maximum;
+// RMAX_BOUND: no maximum is taken.
 template <class S>
 __global__ void k_bin(Geom g, uint64_t n) {
     __shared__ uint32_t cnt[16];
-    uint32_t k = blockIdx.x;
+    const uint32_t f = blockIdx.x;
+    const bool two = g.lpd == 4;
+    CycleDraw cd = cycle_draw(g.seed, n, two);
+    uint32_t k;
+    int s;
+    line_of(g, f, cd.colour, k, s);
     if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
     __syncthreads();
-    CycleDraw cd = cycle_draw(g.seed, n);
-    int ox, oy, oz;
-    octant_origin(g, k, cd.colour, ox, oy, oz);
-    for (uint32_t q = threadIdx.x; q < g.h3; q += blockDim.x) {
-        int x = ox + (int)(q % g.h), y = oy + (int)((q / g.h) % g.h), z = oz + (int)(q / g.h2);
-        int s = S::get(g, x, y, z);
-        int c = (s > 0 ? 7 : 0) + aligned_count<S>(g, x, y, z, s);
-        atomicAdd(&cnt[c], 1u);
-    }
+    bin_octant<S>(g, k, s, cnt);
     __syncthreads();
+    double Rk = 0.0;
     if (threadIdx.x == 0) {
-        double Rk = line_total(cnt, g.r);
-        g.Rk[k] = Rk;
-        for (int c = 0; c < 16; ++c) g.hist[(uint64_t)k * 16 + c] = c < 14 ? cnt[c] : 0;
-        atomicMax((unsigned long long *)&g.st->rmax[0], (unsigned long long)double_to_bits(Rk));
+        Rk = line_total(cnt, g.r);
+        g.Rk[f] = Rk;
+        for (int c = 0; c < 16; ++c) g.hist[(uint64_t)f * 16 + c] = c < 14 ? cnt[c] : 0;
     }
+    if (g.variant & SPKMC_VARIANT_RMAX_BOUND) return;
+    if (g.variant & SPKMC_VARIANT_RMAX_ALL) {
+        for (int o = 0; o < 8; ++o) {
+            if (o == s || (two && o != (s ^ 1))) continue;
+            __syncthreads();
+            if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
+            __syncthreads();
+            bin_octant<S>(g, k, o, cnt);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double Ro = line_total(cnt, g.r);
+                if (Ro > Rk) Rk = Ro;
+            }
+        }
+    }
+    if (threadIdx.x == 0) atomicMax((unsigned long long *)&g.st->rmax[0], (unsigned long long)double_to_bits(Rk));
 }
 
 // Steps 3, 4, 4b and the flip.  One 64-lane wavefront per domain, four per workgroup.
@@ -145,20 +186,23 @@ template <class S>
 __global__ void __launch_bounds__(256) k_select(Geom g, uint64_t n) {
     __shared__ long long part[4][3];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t k = blockIdx.x * 4 + wave;
+    const uint32_t f = blockIdx.x * 4 + wave;  // frequency line
     long long fired = 0, dM = 0, dB = 0;
-    if (k < g.K) {
-        CycleDraw cd = cycle_draw(g.seed, n);
-        double Rmax = bits_to_double(g.st->rmax[0]);
-        U4 dw = philox10((uint32_t)n, (uint32_t)(n >> 32), k, (uint32_t)cd.colour, g.seed);
+    if (f < g.K * g.lpd) {
+        CycleDraw cd = cycle_draw(g.seed, n, g.lpd == 4);
+        uint32_t k;
+        int so;
+        line_of(g, f, cd.colour, k, so);
+        double Rmax = (g.variant & SPKMC_VARIANT_RMAX_BOUND) ? g.rbound : bits_to_double(g.st->rmax[0]);
+        U4 dw = philox10((uint32_t)n, (uint32_t)(n >> 32), k, (uint32_t)so, g.seed);
         double target = unit53(dw.x, dw.y) * Rmax;
         uint32_t cnt[14];
-        for (int c = 0; c < 14; ++c) cnt[c] = g.hist[(uint64_t)k * 16 + c];
+        for (int c = 0; c < 14; ++c) cnt[c] = g.hist[(uint64_t)f * 16 + c];
         int cs = line_select(cnt, g.r, target);
         if (cs >= 0) {
             uint32_t j = mul_index(dw.z, cnt[cs]);
             int ox, oy, oz;
-            octant_origin(g, k, cd.colour, ox, oy, oz);
+            octant_origin(g, k, so, ox, oy, oz);
             for (uint32_t q0 = 0; q0 < g.h3; q0 += 64) {
                 uint32_t q = q0 + lane;
                 int x = 0, y = 0, z = 0, s = 0, a = 0;
@@ -180,10 +224,10 @@ __global__ void __launch_bounds__(256) k_select(Geom g, uint64_t n) {
                         if (g.layout == SPKMC_LAYOUT_INT8) {
                             g.spin8[(int64_t)x + (int64_t)g.L * ((int64_t)y + (int64_t)g.L * z)] = (int8_t)(-s);
                         } else {
-                            uint64_t bit = ((uint64_t)k * 8 + (uint64_t)cd.colour) * g.h3 + q;
+                            uint64_t bit = ((uint64_t)k * 8 + (uint64_t)so) * g.h3 + q;
                             atomicXor(&g.A[bit >> 5], 1u << (bit & 31));
                             uint32_t lx = q % g.h, ly = (q / g.h) % g.h, lz = q / g.h2;
-                            uint32_t *F = g.F + ((uint64_t)k * 8 + (uint64_t)cd.colour) * g.fwpo;
+                            uint32_t *F = g.F + ((uint64_t)k * 8 + (uint64_t)so) * g.fwpo;
                             uint32_t e = g.h - 1;
                             uint32_t fidx[6] = {lx == 0 ? ly + g.h * lz : ~0u, lx == e ? g.h2 + ly + g.h * lz : ~0u,
                                                 ly == 0 ? 2 * g.h2 + lx + g.h * lz : ~0u,
@@ -232,13 +276,14 @@ __global__ void __launch_bounds__(256) k_select(Geom g, uint64_t n) {
 __global__ void k_finalize(Geom g, uint64_t n, uint32_t obs_every) {
     if (threadIdx.x != 0) return;
     DevState *st = g.st;
-    CycleDraw cd = cycle_draw(g.seed, n);
-    double Rmax = bits_to_double(st->rmax[0]);
-    double dt = -log(cd.ut) / (8.0 * Rmax);
+    const bool two = g.lpd == 4;
+    CycleDraw cd = cycle_draw(g.seed, n, two);
+    double Rmax = (g.variant & SPKMC_VARIANT_RMAX_BOUND) ? g.rbound : bits_to_double(st->rmax[0]);
+    double dt = -log(cd.ut) / ((two ? 2.0 : 8.0) * Rmax);
     st->t = st->t + dt;
     uint64_t f = st->acc_fired[0];
     st->fired += f;
-    st->nulls += (uint64_t)g.K - f;
+    st->nulls += (uint64_t)g.K * g.lpd - f;
     st->M += st->acc_dM[0];
     st->B += st->acc_dB[0];
     st->acc_fired[0] = 0;
@@ -290,12 +335,13 @@ hipError_t launch_observables(const Geom &g, hipStream_t stream) {
 
 hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream_t stream) {
     unsigned bin_block = g.h3 >= 256 ? 256 : 64;
-    unsigned sel_blocks = (g.K + 3) / 4;
+    const unsigned lines = g.K * g.lpd;
+    unsigned sel_blocks = (lines + 3) / 4;
     if (g.layout == SPKMC_LAYOUT_INT8) {
-        hipLaunchKernelGGL(k_bin<Int8Spins>, dim3(g.K), dim3(bin_block), 0, stream, g, n);
+        hipLaunchKernelGGL(k_bin<Int8Spins>, dim3(lines), dim3(bin_block), 0, stream, g, n);
         hipLaunchKernelGGL(k_select<Int8Spins>, dim3(sel_blocks), dim3(256), 0, stream, g, n);
     } else {
-        hipLaunchKernelGGL(k_bin<PackedSpins>, dim3(g.K), dim3(bin_block), 0, stream, g, n);
+        hipLaunchKernelGGL(k_bin<PackedSpins>, dim3(lines), dim3(bin_block), 0, stream, g, n);
         hipLaunchKernelGGL(k_select<PackedSpins>, dim3(sel_blocks), dim3(256), 0, stream, g, n);
     }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, stream, g, n, obs_every);

@@ -54,9 +54,10 @@ constexpr uint64_t kTimeoutTicks = 200000000ull;  // 2 s of the 100 MHz wall clo
 
 // Device scratch of the persistent engine (its own region of the state).
 struct PersistScratch {
-    uint64_t *slot;  // 2 x G: R_max of each workgroup, generation bit 63
-    uint64_t *flag;  // G: cycles whose flips are complete
-    int64_t *recp;   // kRecBanks x G x 3: counter partials (fired, dM, dB) since launch start
+    uint64_t *slot;     // 2 x G: R_max of each workgroup, generation bit 63
+    uint64_t *flag;     // G: cycles whose flips are complete
+    int64_t *recp;      // kRecBanks x G x 3: counter partials (fired, dM, dB) since launch start
+    uint64_t *emitted;  // records of this launch appended so far (fixed-bound variant)
 };
 constexpr uint64_t kScratchWordsPerWg = 2 + 1 + 3 * kRecBanks;
 
@@ -538,6 +539,32 @@ __device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch 
     }
 }
 
+// Wait until the neighbour workgroups in direction dir (all six directions for
+// dir < 0) have completed `upto` cycles; false on a timeout (error set).
+template <int BLOCK>
+__device__ __forceinline__ bool wait_neighbours(const PersistScratch &xs, DevState *st, PersistShared &sh, uint32_t G,
+                                                int dir, uint64_t upto) {
+    const int tid = threadIdx.x;
+    for (int d = dir < 0 ? 0 : dir; d < (dir < 0 ? 6 : dir + 1); ++d) {
+        const bool all = sh.nbr_cnt[d] > kMaxNbr;
+        const uint32_t cnt = all ? G : sh.nbr_cnt[d];
+        for (uint32_t i = tid; i < cnt; i += BLOCK) {
+            const uint32_t w = all ? i : sh.nbr[d][i];
+            const uint64_t start = now_ticks();
+            while (ld64(&xs.flag[w]) < upto) {
+                __builtin_amdgcn_s_sleep(1);
+                if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
+                    atomicOr(&st->error, kErrFlagTimeout);
+                    sh.abort = 1;
+                    break;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    return !sh.abort;
+}
+
 // Bin octant o of every domain of the workgroup (the 13 moments of each row, then
 // its histogram) into the packed counts of that octant.
 template <int H, int P, int BLOCK>
@@ -645,33 +672,26 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     long long myF = 0, mydM = 0, mydB = 0;  // this thread's share since launch start
     uint32_t rec_index = 0;                  // records produced in this launch
     int prev_colour = -1;
+    const bool bound = (g.variant & SPKMC_VARIANT_RMAX_BOUND) != 0;   // re-binning engine only
+    const bool rmax_all = INC && (g.variant & SPKMC_VARIANT_RMAX_ALL);  // incremental engine only
 
     for (uint64_t n = n0; n < n_end; ++n) {
         CycleDraw cd = cycle_draw(g.seed, n);
         const int s = cd.colour;
 
-        // --- step 6 of the previous cycle: wait for the neighbour flips the halo of colour s can see
+        // --- step 6 of the previous cycle: wait for the neighbour flips the halo of colour s can see.
+        // With the fixed bound (no R_max exchange) or the all-octant maximum (every
+        // octant's counts are needed) the wait covers every neighbour every cycle.
         if (n > n0) {
-            int diff = s ^ prev_colour;
-            if (diff && !(diff & (diff - 1))) {
-                int a = diff == 1 ? 0 : diff == 2 ? 1 : 2;
-                int dir = 2 * a + ((s >> a) & 1);  // below (-) if bit a of s is 0, else above (+)
-                const bool all = sh.nbr_cnt[dir] > kMaxNbr;
-                const uint32_t cnt = all ? G : sh.nbr_cnt[dir];
-                for (uint32_t i = tid; i < cnt; i += nthr) {
-                    uint32_t w = all ? i : sh.nbr[dir][i];
-                    uint64_t start = now_ticks();
-                    while (ld64(&xs.flag[w]) < n) {
-                        __builtin_amdgcn_s_sleep(1);
-                        if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
-                            atomicOr(&st->error, kErrFlagTimeout);
-                            sh.abort = 1;
-                            break;
-                        }
-                    }
+            if (bound || rmax_all) {
+                if (!wait_neighbours<BLOCK>(xs, st, sh, G, -1, n)) break;
+            } else {
+                int diff = s ^ prev_colour;
+                if (diff && !(diff & (diff - 1))) {
+                    int a = diff == 1 ? 0 : diff == 2 ? 1 : 2;
+                    int dir = 2 * a + ((s >> a) & 1);  // below (-) if bit a of s is 0, else above (+)
+                    if (!wait_neighbours<BLOCK>(xs, st, sh, G, dir, n)) break;
                 }
-                __syncthreads();
-                if (sh.abort) break;
             }
         }
         prev_colour = s;
@@ -680,7 +700,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         if constexpr (INC) {
             // --- fold the class changes other workgroups pushed into octant s (and,
             // every kFoldAll cycles, into all octants)
-            const bool fold_all = (n - n0) % kFoldAll == kFoldAll - 1;
+            const bool fold_all = rmax_all || (n - n0) % kFoldAll == kFoldAll - 1;
 #pragma unroll 1
             for (int o = 0; o < 8; ++o) {
                 if (o != s && !fold_all) continue;
@@ -694,7 +714,8 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                 }
             }
             __syncthreads();
-            // --- step 1: frequency line of every domain from its counts
+            // --- step 1: frequency line of every domain from its counts (with the
+            // all-octant maximum, rk is the largest line of the domain's octants)
             for (uint32_t i = tid; i < D; i += nthr) {
                 const uint32_t *hp = sh.histp[i][s];
                 double a = 0.0;
@@ -703,7 +724,19 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                     a = a + term;
                     sh.acc[i][c] = a;
                 }
-                sh.rk[i] = i < nvalid ? a : 0.0;
+                double m = a;
+                if (rmax_all) {
+                    for (int o = 0; o < 8; ++o) {
+                        const uint32_t *ho = sh.histp[i][o];
+                        double b = 0.0;
+                        for (int c = 0; c < 14; ++c) {
+                            double term = (double)hcount(ho, c) * sh.r[c];
+                            b = b + term;
+                        }
+                        m = fmax(m, b);
+                    }
+                }
+                sh.rk[i] = i < nvalid ? m : 0.0;
             }
             __syncthreads();
         } else {
@@ -754,7 +787,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         // bank n & 1 holds cycles n - 2 and n; the generation bit tells them apart
         uint64_t *bank = xs.slot + (n & 1) * (uint64_t)G;
         const uint64_t gen = ((n >> 1) & 1) << 63;
-        if (tid < 64) {
+        if (tid < 64 && !bound) {
             double v = 0.0;
             for (uint32_t i = tid; i < D; i += 64) v = fmax(v, sh.rk[i]);
             for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -777,7 +810,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                 compute_octant<H, false>(raw[pp & 1], valid, l, sh.zbuf[row], pl[pp], m);
             }
         }
-        if (tid < 64) {
+        if (tid < 64 && !bound) {
             // workgroup 0 sums a record stored two or more cycles ago while it waits
             if (recorder && sh.pend_head != sh.pend_tail && sh.pend_cycle[sh.pend_head % kRecBanks] + 2 <= n + 1)
                 emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
@@ -819,7 +852,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         }
         __syncthreads();
         if (sh.abort) break;
-        const double Rmax = sh.rmax;
+        const double Rmax = bound ? g.rbound : sh.rmax;
 
         // --- steps 3, 4 and 4b: event or null in every domain
         if (tid == 0) sh.nflip = 0;
@@ -1001,6 +1034,20 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                     atomicAdd((unsigned long long *)&st->B, (unsigned long long)dB);
                 } else {
                     const uint32_t bank = rec_index % kRecBanks;
+                    if (bound) {
+                        // no R_max exchange keeps the workgroups within a cycle of one
+                        // another: before reusing a bank wait until workgroup 0 has
+                        // appended the record that used it
+                        const uint64_t start = now_ticks();
+                        while (ld64(xs.emitted) + kRecBanks <= rec_index) {
+                            __builtin_amdgcn_s_sleep(1);
+                            if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
+                                atomicOr(&st->error, kErrFlagTimeout);
+                                sh.abort = 1;
+                                break;
+                            }
+                        }
+                    }
                     int64_t *rp = xs.recp + (uint64_t)bank * G * 3;
                     st64((uint64_t *)&rp[3 * gid], (uint64_t)F);
                     st64((uint64_t *)&rp[3 * gid + 1], (uint64_t)dM);
@@ -1019,6 +1066,30 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         if (tid == 0) {
             __builtin_amdgcn_s_waitcnt(0);
             st64(&xs.flag[gid], n + 1);
+        }
+        if (bound && record && !last) {  // uniform over the workgroup
+            if (recorder && tid < 64) {
+                // fixed bound: workgroup 0 appends the record as soon as every
+                // workgroup has completed the cycle (its own flag is already out)
+                const uint64_t start = now_ticks();
+                bool ok = true;
+                for (uint32_t w = tid; w < G && ok; w += 64)
+                    while (ld64(&xs.flag[w]) < n + 1) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
+                            atomicOr(&st->error, kErrFlagTimeout);
+                            sh.abort = 1;
+                            ok = false;
+                            break;
+                        }
+                    }
+                if (__all(ok)) {
+                    emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
+                    if (tid == 0) st64(xs.emitted, (uint64_t)rec_index);
+                }
+            }
+            __syncthreads();
+            if (sh.abort) break;
         }
     }
 
@@ -1092,6 +1163,7 @@ __device__ __forceinline__ void prep_one(const PersistScratch &xs, uint32_t G, u
     // bank b first serves cycle nb (n0 or n0 + 1, nb & 1 == b): mark it "not yet"
     for (uint64_t nb = n0; nb < n0 + 2; ++nb) xs.slot[(nb & 1) * G + i] = (((nb >> 1) + 1) & 1) << 63;
     xs.flag[i] = n0;
+    if (i == 0) *xs.emitted = 0;
 }
 // and (incremental engine) no pushed class changes pending: the launch starts
 // from histograms binned afresh.
@@ -1138,10 +1210,14 @@ static void *select_kernel(int h, int P, int block, bool batch = false, bool inc
     return nullptr;
 }
 
-bool persistent_supported(const Geom &g, const spkmc_params &p, std::string &why) {
+bool persistent_supported(const Geom &g, const spkmc_params &p, bool inc, std::string &why) {
     if (g.layout != SPKMC_LAYOUT_PACKED) { why = "needs the PACKED layout"; return false; }
     if (g.h != 8 && g.h != 16) { why = "needs an octant edge of 8 or 16 (domain 16 or 32)"; return false; }
-    const bool inc = p.engine == SPKMC_ENGINE_INCREMENTAL;
+    const uint32_t ok = inc ? SPKMC_VARIANT_RMAX_ALL : SPKMC_VARIANT_RMAX_BOUND;
+    if (p.variant & ~ok) {
+        why = inc ? "the incremental engine runs variants 0 and RMAX_ALL" : "this engine runs variants 0 and RMAX_BOUND";
+        return false;
+    }
     const int rows = persist_rows(g.h, inc), pmax = persist_max_passes(g.h, inc);
     const int pc = p.wg_domains / rows;
     if (p.wg_domains && (p.wg_domains % rows || pc > pmax || (pc & (pc - 1)))) {
@@ -1188,6 +1264,7 @@ PersistScratch scratch_of(const Geom &g, int G) {
     xs.slot = g.sync;
     xs.flag = g.sync + 2 * (uint64_t)G;
     xs.recp = reinterpret_cast<int64_t *>(g.sync + 3 * (uint64_t)G);
+    xs.emitted = g.sync + 15 * (uint64_t)G;  // within the 16 spare words
     return xs;
 }
 

@@ -56,7 +56,14 @@ struct LayoutPlan {
 static bool validate(const spkmc_params *p, std::string &why) {
     if (!p) { why = "params is NULL"; return false; }
     if (p->struct_size != sizeof(spkmc_params)) { why = "struct_size does not match sizeof(spkmc_params)"; return false; }
-    if (p->reserved != 0) { why = "reserved must be 0"; return false; }
+    if (p->variant & ~(uint32_t)(SPKMC_VARIANT_RMAX_ALL | SPKMC_VARIANT_TWO_COLOURS | SPKMC_VARIANT_RMAX_BOUND)) {
+        why = "unknown variant bits";
+        return false;
+    }
+    if ((p->variant & SPKMC_VARIANT_RMAX_ALL) && (p->variant & SPKMC_VARIANT_RMAX_BOUND)) {
+        why = "RMAX_ALL and RMAX_BOUND exclude each other";
+        return false;
+    }
     if (p->L < 2) { why = "L must be >= 2"; return false; }
     if (p->domain < 2 || (p->domain & 1)) { why = "domain edge must be even and >= 2"; return false; }
     if (p->L % p->domain) { why = "L must be a multiple of the domain edge"; return false; }
@@ -82,8 +89,9 @@ static LayoutPlan plan(const spkmc_params *p) {
     size_t o = 256;  // DevState
     lp.off_rates = o; o += 256;
     lp.off_rec = o; o = align256(o + (size_t)p->record_cap * sizeof(spkmc_record));
-    lp.off_Rk = o; o = align256(o + K * 8);
-    lp.off_hist = o; o = align256(o + K * 64);
+    const uint64_t lines = K * ((p->variant & SPKMC_VARIANT_TWO_COLOURS) ? 4 : 1);
+    lp.off_Rk = o; o = align256(o + lines * 8);
+    lp.off_hist = o; o = align256(o + lines * 64);
     lp.off_flip = o; o = align256(o + K * 8);
     // persistent engine: slots, flags and record partials of its workgroups, and
     // the class changes its workgroups push to one another (PACKED)
@@ -173,6 +181,8 @@ spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, 
     g.wpo = g.h3 / 32;
     g.fwpo = 6 * g.h2 / 32;
     g.rec_cap = p->record_cap;
+    g.variant = p->variant;
+    g.lpd = (p->variant & SPKMC_VARIANT_TWO_COLOURS) ? 4u : 1u;
     g.seed = p->seed;
     g.st = (DevState *)c->dev;
     g.rec = (spkmc_record *)(c->dev + lp.off_rec);
@@ -188,18 +198,29 @@ spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, 
         g.F = (uint32_t *)(c->dev + lp.off_F);
     }
     make_rates(p, g.r);
+    {   // R'_max: the sites of one line times the largest class rate
+        double rb = g.r[0];
+        for (int cc = 1; cc < 14; ++cc)
+            if (g.r[cc] > rb) rb = g.r[cc];
+        g.rbound = (double)((int64_t)g.h * g.h * g.h) * rb;
+        g.pad2 = 0;
+    }
     c->spin_off = lp.off_spin;
     c->spin_bytes = lp.spin_bytes;
     c->rec_off = lp.off_rec;
 
-    // engine choice
+    // engine choice: the incremental engine for an explicit request or for the
+    // all-octant R_max (its histograms of every octant stay resident), else the
+    // re-binning persistent engine, else the per-cycle engine
     std::string pwhy;
-    bool pers = persistent_supported(g, *p, pwhy);
+    const bool want_inc = p->engine == SPKMC_ENGINE_INCREMENTAL ||
+                          (p->engine == SPKMC_ENGINE_AUTO && (p->variant & SPKMC_VARIANT_RMAX_ALL));
+    bool pers = persistent_supported(g, *p, want_inc, pwhy);
     const bool want_pers = p->engine == SPKMC_ENGINE_PERSISTENT || p->engine == SPKMC_ENGINE_INCREMENTAL;
     if (want_pers && !pers) return fail(c, SPKMC_E_UNSUPPORTED, "persistent engine: " + pwhy);
     c->engine = (p->engine == SPKMC_ENGINE_CYCLE || !pers) ? SPKMC_ENGINE_CYCLE
-                : p->engine == SPKMC_ENGINE_INCREMENTAL ? SPKMC_ENGINE_INCREMENTAL
-                                                        : SPKMC_ENGINE_PERSISTENT;
+                : want_inc                            ? SPKMC_ENGINE_INCREMENTAL
+                                                      : SPKMC_ENGINE_PERSISTENT;
     c->grid = (int)g.K;
     c->block = 256;
     c->wg_domains = 0;
@@ -476,7 +497,7 @@ spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *n
         if (c->failed || !c->dev) return fail(nullptr, SPKMC_E_STATE, "a context of the batch is in a failed state");
         if (ncycles[i] == 0) continue;
         std::string why;
-        if (!persistent_supported(c->g, c->p, why)) return fail(nullptr, SPKMC_E_UNSUPPORTED, "batch member: " + why);
+        if (!persistent_supported(c->g, c->p, false, why)) return fail(nullptr, SPKMC_E_UNSUPPORTED, "batch member: " + why);
         if (live.empty()) {
             stream = c->stream;
             h = c->g.h;

@@ -44,7 +44,7 @@ struct Geom {
     uint32_t wpo;          // PACKED: 32-bit words per octant (h^3 / 32)
     uint32_t fwpo;         // PACKED: face words per octant (6 h^2 / 32)
     uint32_t rec_cap;
-    uint32_t pad;
+    uint32_t variant;      // SPKMC_VARIANT_* bits
     uint64_t seed;
     DevState *st;
     spkmc_record *rec;
@@ -57,6 +57,9 @@ struct Geom {
     uint32_t *A;           // PACKED spins, octant-major, canonical order inside an octant
     uint32_t *F;           // PACKED face copies: per octant x0, x1, y0, y1, z0, z1 (h^2 bits each)
     double r[14];          // rate table
+    double rbound;         // R'_max = n_k max_c r_c (RMAX_BOUND)
+    uint32_t lpd;          // frequency lines per domain and cycle: 1, or 4 (TWO_COLOURS)
+    uint32_t pad2;
 };
 
 // ---------------------------------------------------------------------------
@@ -98,14 +101,20 @@ __host__ __device__ inline uint32_t mul_index(uint32_t w, uint32_t n) {
     return (uint32_t)(((uint64_t)w * n) >> 32);
 }
 
-// The per-cycle draw shared by every domain: colour and the clock uniform.
+// The per-cycle draw shared by every domain: colour (top 3 bits of the first
+// word; with two colours its top bit) and the clock uniform.
 struct CycleDraw {
     int colour;
     double ut;
 };
-__host__ __device__ inline CycleDraw cycle_draw(uint64_t seed, uint64_t n) {
+__host__ __device__ inline CycleDraw cycle_draw(uint64_t seed, uint64_t n, bool two_colours = false) {
     U4 w = philox10((uint32_t)n, (uint32_t)(n >> 32), 0xFFFFFFFFu, 0xFFFFFFFFu, seed);
-    return CycleDraw{(int)(w.x >> 29), unit_open52(w.z, w.w)};
+    return CycleDraw{(int)(w.x >> (two_colours ? 31 : 29)), unit_open52(w.z, w.w)};
+}
+// Octant of the i-th frequency line (i < 4) of colour c with two colours: the
+// octants whose sx + sy + sz has parity c, in increasing order.
+__host__ __device__ inline int two_colour_octant(int c, uint32_t i) {
+    return c ? (int)((0x7421u >> (4 * i)) & 15u) : (int)((0x6530u >> (4 * i)) & 15u);
 }
 
 // Fixed-order FP64 frequency line: separate multiply and add, classes 0..13.

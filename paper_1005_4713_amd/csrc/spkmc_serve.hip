@@ -198,7 +198,7 @@ static spkmc_status admit(spkmc_server *s) {
         }
         std::string why;
         const int h = r.ctx->g.h;
-        r.batched = persistent_supported(r.ctx->g, r.ctx->p, why) &&
+        r.batched = persistent_supported(r.ctx->g, r.ctx->p, false, why) &&
                     batch_wgs(r.ctx->g, persist_max_passes(h, false)) <= s->cap[h == 16];
         r.state = SPKMC_REQ_RUNNING;
         s->live.push_back(r.id);

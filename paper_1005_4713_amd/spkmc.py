@@ -17,13 +17,14 @@ RATES = {"glauber": 0, "metropolis": 1}
 INITS = {"random": 0, "up": 1, "down": 2}
 LAYOUTS = {"int8": 0, "packed": 1}
 ENGINES = {"auto": 0, "cycle": 1, "persistent": 2, "incremental": 3}
+VARIANTS = {"rmax_all": 1, "two_colours": 2, "rmax_bound": 4}
 
 
 class Params(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("L", C.c_int32), ("domain", C.c_int32), ("rates", C.c_int32),
                 ("J", C.c_double), ("H", C.c_double), ("T", C.c_double), ("seed", C.c_uint64),
                 ("init", C.c_int32), ("layout", C.c_int32), ("engine", C.c_int32), ("wg_domains", C.c_int32),
-                ("record_cap", C.c_uint32), ("reserved", C.c_uint32)]
+                ("record_cap", C.c_uint32), ("variant", C.c_uint32)]
 
 
 class Record(C.Structure):
@@ -149,7 +150,7 @@ class SpkmcError(RuntimeError):
 
 
 def make_params(L, domain, J=1.0, H=0.0, T=4.5115, seed=1, rates="glauber", init="random",
-                layout="packed", engine="auto", wg_domains=0, record_cap=1024):
+                layout="packed", engine="auto", wg_domains=0, record_cap=1024, variant=0):
     p = Params()
     p.struct_size = C.sizeof(Params)
     p.L, p.domain = int(L), int(domain)
@@ -161,7 +162,9 @@ def make_params(L, domain, J=1.0, H=0.0, T=4.5115, seed=1, rates="glauber", init
     p.engine = ENGINES[engine] if isinstance(engine, str) else int(engine)
     p.wg_domains = int(wg_domains)
     p.record_cap = int(record_cap)
-    p.reserved = 0
+    if isinstance(variant, str):
+        variant = sum(VARIANTS[v] for v in variant.split("|") if v)
+    p.variant = int(variant)
     return p
 
 

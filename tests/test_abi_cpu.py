@@ -66,9 +66,12 @@ def test_struct_size_checked(spkmc):
     p = spkmc.make_params(16, 8)
     p.struct_size = 64
     assert spkmc.state_bytes(p) == 0
-    p = spkmc.make_params(16, 8)
-    p.reserved = 1
-    assert spkmc.state_bytes(p) == 0
+    for bad in (8, 16, 1 | 4, 1 | 2 | 4):  # unknown bits; RMAX_ALL with RMAX_BOUND
+        p = spkmc.make_params(16, 8)
+        p.variant = bad
+        assert spkmc.state_bytes(p) == 0, bad
+    for ok in (0, 1, 2, 4, 1 | 2, 2 | 4):
+        assert spkmc.state_bytes(spkmc.make_params(16, 8, variant=ok)) > 0, ok
 
 
 def test_buffer_too_small_rejected(spkmc):
@@ -178,3 +181,10 @@ def test_server_calls_reject_null(spkmc):
     assert spkmc.lib.spkmc_server_release(None, 1) == spkmc.E_INVAL
     assert spkmc.lib.spkmc_server_clock(None) == 0.0
     spkmc.lib.spkmc_server_destroy(None)
+
+
+def test_two_colours_sizes_four_lines_per_domain(spkmc):
+    one = spkmc.state_bytes(spkmc.make_params(64, 16))
+    two = spkmc.state_bytes(spkmc.make_params(64, 16, variant="two_colours"))
+    K = (64 // 16) ** 3
+    assert two - one >= 3 * K * (8 + 64) - 512  # R_k and histogram of three more lines per domain
