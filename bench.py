@@ -32,7 +32,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500, help="timed cycles")
     ap.add_argument("--warmup", type=int, default=50, help="untimed cycles before the timed region")
-    ap.add_argument("--workload", default="headline", choices=["headline", "l512", "l128", "batch", "serve"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "l512", "l128", "batch", "serve", "zeff"])
+    ap.add_argument("--variant", default="", help="method variant bits by name, e.g. rmax_bound or two_colours|rmax_all")
+    ap.add_argument("--zeff-L", type=int, default=512, help="zeff: lattice edge")
+    ap.add_argument("--zeff-tmax", type=float, default=400.0, help="zeff: simulated time to reach")
     ap.add_argument("--replicas", type=int, default=256, help="batch / serve: lattices in the replica mix")
     ap.add_argument("--cycles", type=int, default=1000, help="batch / serve: cycles per lattice")
     ap.add_argument("--macro-cycles", type=int, default=100, help="serve: cycles per macro-step")
@@ -68,7 +71,7 @@ def calibrate_copy(mib):
     print(json.dumps({"calibrate_copy_bytes": n, "copies": 3, "read_bytes_per_copy": n, "write_bytes_per_copy": n}))
 
 
-def measured_traffic(workload_name, kernel, steps):
+def measured_traffic(workload_name, kernel, variant, steps):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary of this kernel and workload (each scaled by the reading of a plain
     copy of known size); None if there is none or the kernel source changed
@@ -78,7 +81,8 @@ def measured_traffic(workload_name, kernel, steps):
     for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")):
         with open(path) as f:
             rec = json.load(f)
-        if rec.get("workload") != workload_name or rec.get("kernel") != kernel:
+        if (rec.get("workload") != workload_name or rec.get("kernel") != kernel
+                or rec.get("variant", "contract") != variant):
             continue
         m = hashlib.sha256()
         for name in rec["source_files"]:
@@ -153,6 +157,49 @@ def _serve_run(spkmc, specs, doms, arrivals, pool_bytes, macro, max_live, log):
     log(f"serve: {n} requests, p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms, "
         f"makespan {span:.3f} s, pool peak {st['pool_peak'] / 2**20:.1f} MiB")
     return out, [r["state_tuple"] for r in res]
+
+
+def bench_zeff(args):
+    """Sec. 5 analysis (eqs. 16-17): magnetisation relaxation from all +1 at
+    T_c, m(t) ~ t^(-beta / (nu z)); the effective exponent from the log-slope
+    over sliding windows, z_eff = -(beta/nu) / (d ln m / d ln t), with the
+    paper's beta/nu = 0.515.  Time in units of 1/lambda (lambda = 1)."""
+    import torch
+    from paper_1005_4713_amd import spkmc
+    L = args.zeff_L
+    d = 32 if L >= 1024 else 16
+    sim = spkmc.Sim(L, d, layout="packed", init="up", T=4.5115, seed=77, variant=args.variant or 0,
+                    record_cap=1 << 16)
+    obs = 50 if L >= 1024 else 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chunk = 20000
+    recs = []
+    while sim.state()[3] < args.zeff_tmax:
+        sim.run(chunk, obs_every=obs)
+        recs += sim.records(chunk // obs)
+        print(f"zeff: t = {sim.state()[3]:.1f}", file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    t = np.array([r[3] for r in recs])
+    m = np.array([r[4] for r in recs], dtype=np.float64) / float(L) ** 3
+    beta_over_nu = 0.515
+    windows = []
+    lo = 1.0
+    while lo * 2 <= t[-1]:
+        sel = (t >= lo) & (t <= 2 * lo) & (m > 0)
+        if sel.sum() >= 5:
+            slope = np.polyfit(np.log(t[sel]), np.log(m[sel]), 1)[0]
+            windows.append({"t_lo": lo, "t_hi": 2 * lo, "inv_t_mid": 1.0 / (1.5 * lo), "slope": slope,
+                            "z_eff": -beta_over_nu / slope if slope < 0 else None})
+        lo *= 2 ** 0.5
+    st = sim.state()
+    out = {"metric": "z_eff(t) from m(t) ~ t^(-beta/(nu z)), all +1 start at T_c", "value": windows[-1]["z_eff"],
+           "unit": "dimensionless", "n_gpus": 1, "higher_is_better": None, "data": "synthetic", "dtype": "u32+f64",
+           "config": {"workload": f"L{L}_d{d}_packed_Tc_up", "variant": args.variant or "contract",
+                      "beta_over_nu": beta_over_nu, "cycles": st[0], "t_end": st[3]},
+           "wall_s": wall, "events_per_s": st[1] / wall, "windows": windows,
+           "m_t": [[float(a), float(b)] for a, b in zip(t[::max(1, len(t) // 200)], m[::max(1, len(m) // 200)])]}
+    print(json.dumps(out), flush=True)
 
 
 def bench_serve(args):
@@ -267,12 +314,17 @@ def main():
         torch.cuda.set_device(0)
         bench_serve(args)
         return
+    if args.workload == "zeff":
+        torch.cuda.set_device(0)
+        bench_zeff(args)
+        return
     w = workload(args.workload)
     torch.cuda.set_device(0)
     print(f"bench: workload {w['name']} engine={args.engine} warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
     sim = spkmc.Sim(w["L"], w["domain"], J=w["J"], H=w["H"], T=w["T"], seed=w["seed"], rates=w["rates"],
                     init=w["init"], layout=w["layout"], engine=args.engine, wg_domains=args.wg_domains,
+                    variant=args.variant or 0,
                     record_cap=max(1, (args.warmup + args.steps) // max(args.obs_every, 1) + 1))
     info = sim.info()
     stream = sim.stream
@@ -304,7 +356,7 @@ def main():
               else "whole cycle (3 launches)")
     traffic, traffic_rec = (None, None)
     if launches == 1:
-        traffic, traffic_rec = measured_traffic(w["name"], kernel, args.steps)
+        traffic, traffic_rec = measured_traffic(w["name"], kernel, args.variant or "contract", args.steps)
     out = {
         "metric": METRIC,
         "value": value,
@@ -322,7 +374,8 @@ def main():
                    "H": w["H"], "rates": w["rates"], "init": w["init"], "seed": w["seed"],
                    "layout": w["layout"], "engine": ["auto", "cycle", "persistent", "incremental"][info["engine"]],
                    "grid": info["grid"], "block": info["block"], "wg_domains": info["wg_domains"],
-                   "K": info["K"], "h": info["h"], "obs_every": args.obs_every},
+                   "K": info["K"], "h": info["h"], "obs_every": args.obs_every,
+                   "variant": args.variant or "contract"},
         "attempts_per_s": (fired + nulls) / secs,
         "ur": fired / max(fired + nulls, 1),
         "wall_s": wall,

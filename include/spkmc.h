@@ -103,8 +103,8 @@ enum { SPKMC_ENGINE_AUTO = 0, SPKMC_ENGINE_CYCLE = 1, SPKMC_ENGINE_PERSISTENT = 
  *   R'_max = n_k max_c r_c (n_k sites per line), so no maximum over lines is
  *   taken; more null events, the same dynamics.
  * RMAX_ALL and RMAX_BOUND exclude each other.  Engines: CYCLE runs every
- * variant; PERSISTENT runs 0 and RMAX_BOUND; INCREMENTAL runs 0 and RMAX_ALL
- * (AUTO picks accordingly). */
+ * variant; PERSISTENT runs every combination of TWO_COLOURS and RMAX_BOUND;
+ * INCREMENTAL runs 0 and RMAX_ALL (AUTO picks accordingly). */
 enum { SPKMC_VARIANT_RMAX_ALL = 1, SPKMC_VARIANT_TWO_COLOURS = 2, SPKMC_VARIANT_RMAX_BOUND = 4 };
 
 typedef struct spkmc_params {

@@ -528,7 +528,7 @@ __device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch 
         spkmc_record r;
         r.cycle = cyc;
         r.fired = fired0 + (uint64_t)F;
-        r.nulls = nulls0 + (uint64_t)g.K * (cyc - n0) - (uint64_t)F;
+        r.nulls = nulls0 + (uint64_t)g.K * g.lpd * (cyc - n0) - (uint64_t)F;
         r.t = sh.pend_t[slot];
         r.M = M0 + dM;
         r.B = B0 + dB;
@@ -617,8 +617,15 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     const int row = tid >> 4, l = tid & 15;  // DPP row and lane inside it
     const uint32_t G = R.G;
     const uint32_t D = (uint32_t)(rows * P);
-    const uint32_t kbase = gid * D;
-    const uint32_t nvalid = kbase >= g.K ? 0u : (g.K - kbase < D ? g.K - kbase : D);
+    // rows run frequency lines: one per domain, or (two colours) the four active
+    // octants of each domain, lines 4k .. 4k + 3 of domain k
+    const uint32_t lpd = g.lpd, NL = g.K * lpd;
+    const uint32_t kbase = gid * D;  // first line of the workgroup
+    const uint32_t nvalid = kbase >= NL ? 0u : (NL - kbase < D ? NL - kbase : D);
+    auto line_dom = [lpd](uint32_t line) { return lpd == 1 ? line : line >> 2; };
+    auto line_oct = [lpd](uint32_t line, int colour) {
+        return lpd == 1 ? colour : two_colour_octant(colour, line & 3u);
+    };
     const bool recorder = gid == 0;
     const uint64_t n_end = n0 + ncycles;
 
@@ -633,7 +640,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     for (uint32_t i = tid; i < nvalid * 6; i += nthr) {
         uint32_t ldm = i / 6;
         int dir = (int)(i % 6), a = dir >> 1;
-        DomainCoord c = dcoord(kbase + ldm, g.nd);
+        DomainCoord c = dcoord(line_dom(kbase + ldm), g.nd);
         int kc[3] = {c.kx, c.ky, c.kz};
         kc[a] = (dir & 1) ? wrapp(kc[a], g.nd) : wrapm(kc[a], g.nd);
         sh.nbdom[ldm][dir] = dindex(kc[0], kc[1], kc[2], g.nd);
@@ -641,7 +648,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     __syncthreads();
     for (uint32_t i = tid; i < nvalid * 6; i += nthr) {
         int dir = (int)(i % 6);
-        uint32_t owner = sh.nbdom[i / 6][dir] / D;
+        uint32_t owner = sh.nbdom[i / 6][dir] * lpd / D;
         if (owner != gid) atomicOr(&sh.nbr_bits[dir][owner >> 5], 1u << (owner & 31));
     }
     __syncthreads();
@@ -676,8 +683,8 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     const bool rmax_all = INC && (g.variant & SPKMC_VARIANT_RMAX_ALL);  // incremental engine only
 
     for (uint64_t n = n0; n < n_end; ++n) {
-        CycleDraw cd = cycle_draw(g.seed, n);
-        const int s = cd.colour;
+        CycleDraw cd = cycle_draw(g.seed, n, lpd == 4);
+        const int s = cd.colour;  // the octant (eight colours) or the parity (two)
 
         // --- step 6 of the previous cycle: wait for the neighbour flips the halo of colour s can see.
         // With the fixed bound (no R_max exchange) or the all-octant maximum (every
@@ -685,6 +692,10 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         if (n > n0) {
             if (bound || rmax_all) {
                 if (!wait_neighbours<BLOCK>(xs, st, sh, G, -1, n)) break;
+            } else if (lpd == 4) {
+                // two colours: after a colour change every face of an active octant
+                // touches the cells flipped in the previous cycle
+                if (s != prev_colour && !wait_neighbours<BLOCK>(xs, st, sh, G, -1, n)) break;
             } else {
                 int diff = s ^ prev_colour;
                 if (diff && !(diff & (diff - 1))) {
@@ -747,7 +758,8 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
 #pragma unroll
             for (int pp = 0; pp < P; ++pp) {
                 const uint32_t ld = (uint32_t)(pp * rows + row);
-                load_octant<H>(g, kbase + ld, s, ld < nvalid, l, sh.nbdom[ld < nvalid ? ld : 0], raw[pp]);
+                load_octant<H>(g, line_dom(kbase + ld), line_oct(kbase + ld, s), ld < nvalid, l,
+                               sh.nbdom[ld < nvalid ? ld : 0], raw[pp]);
             }
 #pragma unroll
             for (int pp = 0; pp < P; ++pp) {
@@ -860,7 +872,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         U4 dw;
         {
             const uint32_t kd = kbase + (uint32_t)((l < P ? l : 0) * rows + row);
-            dw = philox10((uint32_t)n, (uint32_t)(n >> 32), kd, (uint32_t)s, g.seed);
+            dw = philox10((uint32_t)n, (uint32_t)(n >> 32), line_dom(kd), (uint32_t)line_oct(kd, s), g.seed);
         }
         __syncthreads();
 #pragma unroll
@@ -926,14 +938,15 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             const uint32_t i = INC ? t / 3 : t, ax = INC ? t % 3 : 0;
             const uint32_t f = sh.flipq[i];
             const uint32_t ld = f >> 16, cs = (f >> 12) & 15u, q = f & 0xFFFu;
-            const uint32_t k = kbase + ld;
+            const uint32_t k = line_dom(kbase + ld);
+            const int so = line_oct(kbase + ld, s);  // the line's octant
             if constexpr (INC) {
                 // The neighbours' other neighbours do not change in this cycle (one flip
                 // per domain, and same-coloured octants of different domains never
                 // touch), so their classes follow from spins read now, with the flipped
                 // site's spin taken before its flip.  The twelve reads are independent.
                 const int qc[3] = {(int)(q % H), (int)((q / H) % H), (int)(q / (H * H))};
-                const int Q[3] = {(s & 1) * H + qc[0], ((s >> 1) & 1) * H + qc[1], ((s >> 2) & 1) * H + qc[2]};
+                const int Q[3] = {(so & 1) * H + qc[0], ((so >> 1) & 1) * H + qc[1], ((so >> 2) & 1) * H + qc[2]};
                 const uint32_t up = cs >= 7;
                 const int dn = up ? -1 : 1;  // change of the neighbours' up counts
                 const DomainCoord dc = dcoord(k, g.nd);
@@ -975,11 +988,11 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                     }
                 }
                 if (ax != 0) continue;
-                hmove(sh.histp[ld][s], cs, site_class(!up, up ? cs - 7 : 6 - cs));
+                hmove(sh.histp[ld][so], cs, site_class(!up, up ? cs - 7 : 6 - cs));
             }
-            flip_word(g.A + ((uint64_t)k * 8 + s) * g.wpo + (q >> 5), 1u << (q & 31));
+            flip_word(g.A + ((uint64_t)k * 8 + so) * g.wpo + (q >> 5), 1u << (q & 31));
             const uint32_t lx = q % H, ly = (q / H) % H, lz = q / (H * H);
-            uint32_t *F = g.F + ((uint64_t)k * 8 + s) * g.fwpo;
+            uint32_t *F = g.F + ((uint64_t)k * 8 + so) * g.fwpo;
             constexpr uint32_t e = H - 1, h2 = H * H;
             if (lx == 0) { uint32_t b = ly + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
             if (lx == e) { uint32_t b = h2 + ly + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
@@ -994,7 +1007,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
 
         // --- step 5: the clock, identical in every workgroup
         {
-            double dt = -log(cd.ut) / (8.0 * Rmax);
+            double dt = -log(cd.ut) / ((lpd == 4 ? 2.0 : 8.0) * Rmax);
             t = t + dt;
         }
 
@@ -1213,9 +1226,10 @@ static void *select_kernel(int h, int P, int block, bool batch = false, bool inc
 bool persistent_supported(const Geom &g, const spkmc_params &p, bool inc, std::string &why) {
     if (g.layout != SPKMC_LAYOUT_PACKED) { why = "needs the PACKED layout"; return false; }
     if (g.h != 8 && g.h != 16) { why = "needs an octant edge of 8 or 16 (domain 16 or 32)"; return false; }
-    const uint32_t ok = inc ? SPKMC_VARIANT_RMAX_ALL : SPKMC_VARIANT_RMAX_BOUND;
+    const uint32_t ok = inc ? SPKMC_VARIANT_RMAX_ALL : (SPKMC_VARIANT_RMAX_BOUND | SPKMC_VARIANT_TWO_COLOURS);
     if (p.variant & ~ok) {
-        why = inc ? "the incremental engine runs variants 0 and RMAX_ALL" : "this engine runs variants 0 and RMAX_BOUND";
+        why = inc ? "the incremental engine runs variants 0 and RMAX_ALL"
+                  : "this engine runs variants 0, RMAX_BOUND and TWO_COLOURS";
         return false;
     }
     const int rows = persist_rows(g.h, inc), pmax = persist_max_passes(g.h, inc);
@@ -1247,7 +1261,7 @@ hipError_t persistent_configure(const Geom &g, const spkmc_params &p, bool inc, 
         int occ = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, 0);
         if (e != hipSuccess) return e;
-        const uint64_t D = (uint64_t)rows * P, G = (g.K + D - 1) / D;
+        const uint64_t D = (uint64_t)rows * P, G = ((uint64_t)g.K * g.lpd + D - 1) / D;
         if (occ > 0 && G <= (uint64_t)occ * cus && G <= (uint64_t)kMaxGrid) {
             grid = (int)G;
             wg_domains = (int)D;
@@ -1301,7 +1315,7 @@ size_t replica_bytes() { return sizeof(Replica); }
 // Workgroups lattice i needs with `rows_pp` domains per pass and P passes.
 uint32_t batch_wgs(const Geom &g, int P) {
     const uint64_t D = (uint64_t)persist_rows(g.h, false) * P;
-    return (uint32_t)((g.K + D - 1) / D);
+    return (uint32_t)(((uint64_t)g.K * g.lpd + D - 1) / D);
 }
 
 // Workgroups of the batch kernel for octant edge h and P passes that the

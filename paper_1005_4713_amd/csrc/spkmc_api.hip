@@ -95,7 +95,7 @@ static LayoutPlan plan(const spkmc_params *p) {
     lp.off_flip = o; o = align256(o + K * 8);
     // persistent engine: slots, flags and record partials of its workgroups, and
     // the class changes its workgroups push to one another (PACKED)
-    lp.off_sync = o; o = align256(o + persistent_scratch_words(K) * 8);
+    lp.off_sync = o; o = align256(o + persistent_scratch_words(lines) * 8);
     lp.off_dh = o;
     if (p->layout == SPKMC_LAYOUT_PACKED) o = align256(o + K * 16 * 8);
     lp.off_spin = o;

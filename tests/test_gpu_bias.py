@@ -1,0 +1,108 @@
+"""The stochastic bias of the sublattice method (Sec. 4, eqs. 6-7), measured
+on the GPU: magnetisation relaxation from all +1 at the critical temperature
+of a 2^18-spin lattice (L = 64), spkMC with two colours (the configuration of
+the paper's own bias runs) at 32, 256 and 2048 parallel processes against
+the mean of serial BKL runs of the oracle.
+
+The number of parallel processes is the number of subcells per colour: with
+octants of edge h = d / 2 it is 4 (L / d)^3.  Time is in units of 1 / lambda
+(lambda = 1); the paper's own time axis cannot be mapped onto these units, so
+the window is chosen here (0.1 <= t <= 4) rather than copied.
+
+Also run: the eight-colour contract on the persistent engine.
+
+Claim checked (Fig. 4): the time-integrated bias over the window is smaller
+than 3 sigma_b, sigma_b^2 = sigma_p^2 + sigma_s^2 (standard errors of the
+parallel and serial means).  The per-time bias of Fig. 3 and the table of
+Fig. 4 are written to gpurun_out/bias_study.json when that folder exists.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TC = 1.0 / 0.2216546
+L = 64
+GRID = np.geomspace(0.1, 4.0, 14)
+SERIAL_RUNS = 16
+PARALLEL_RUNS = 10
+
+
+@pytest.fixture(scope="module")
+def spkmc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1005_4713_amd import spkmc as mod
+    return mod
+
+
+def _on_grid(records, grid):
+    """m at each grid time: the state after the last cycle whose clock <= t."""
+    t = np.array([r[3] for r in records])
+    M = np.array([r[4] for r in records], dtype=np.float64)
+    idx = np.searchsorted(t, grid, side="right") - 1
+    assert np.all(idx >= 0)
+    return M[idx] / L ** 3
+
+
+def _parallel_curve(spkmc, d, seed, variant, engine):
+    sim = spkmc.Sim(L, d, layout="packed", engine=engine, variant=variant, T=TC, init="up", seed=seed,
+                    record_cap=1 << 18)
+    # one record per cycle; run until the clock passes the window
+    chunk = 512
+    while sim.state()[3] <= GRID[-1]:
+        sim.run(chunk, obs_every=1)
+    recs = sim.records()
+    assert recs[0][0] == 1 and recs[-1][0] == len(recs)  # the ring kept every cycle
+    return _on_grid([(0, 0, 0, 0.0, L ** 3, 0)] + recs, GRID)
+
+
+def _integrated(curves):
+    vals = np.array([np.trapezoid(c, GRID) / (GRID[-1] - GRID[0]) for c in curves])
+    return vals.mean(), vals.std(ddof=1) / math.sqrt(len(vals))
+
+
+@pytest.fixture(scope="module")
+def serial():
+    print("bias study: serial BKL reference", flush=True)
+    curves = []
+    for r in range(SERIAL_RUNS):
+        M, _ = oracle.Bkl(L=L, T=TC, init=1, seed=5000 + r).run_grid(GRID)
+        assert len(M) == len(GRID)
+        curves.append(M / L ** 3)
+    return np.array(curves)
+
+
+_TABLE = []
+
+
+@pytest.mark.parametrize("variant,engine,d", [("two_colours", "persistent", 32), ("two_colours", "persistent", 16),
+                                             ("two_colours", "cycle", 8),
+                                             ("", "persistent", 32), ("", "persistent", 16)])
+def test_bias_within_serial_deviation(spkmc, serial, variant, engine, d):
+    print("bias study:", variant or "eight colours", engine, "d =", d, flush=True)
+    ms, ss = _integrated(serial)
+    par = np.array([_parallel_curve(spkmc, d, 7000 + 100 * d + r, variant, engine) for r in range(PARALLEL_RUNS)])
+    mp, sp = _integrated(par)
+    sigma_b = math.sqrt(sp ** 2 + ss ** 2)
+    colours = 2 if variant else 8
+    subcells = 8 * (L // d) ** 3
+    _TABLE.append({"colours": colours, "engine": engine, "domain": d, "processes": subcells // colours,
+                   "sites_per_subcell": (d // 2) ** 3, "integrated_bias": mp - ms, "sigma_b": sigma_b,
+                   "relative_bias": (mp - ms) / ms,
+                   "bias_t": (par.mean(axis=0) - serial.mean(axis=0)).tolist(),
+                   "sigma_s_t": serial.std(axis=0, ddof=1).tolist()})
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "bias_study.json"), "w") as f:
+            json.dump({"L": L, "T": TC, "grid": GRID.tolist(), "serial_runs": SERIAL_RUNS,
+                       "parallel_runs": PARALLEL_RUNS, "serial_mean_t": serial.mean(axis=0).tolist(),
+                       "serial_integrated": ms, "cases": _TABLE}, f, indent=1)
+    assert abs(mp - ms) < 3 * sigma_b, (variant, d, mp, ms, sigma_b)

@@ -1,8 +1,8 @@
 """GPU parity of the method variants against the CPU oracle: two colours
 (octant parity), the all-octant R_max and the optimistic bound R'_max, on the
 per-cycle engine (every variant, both layouts) and on the persistent engines
-(the bound on the re-binning kernel, the all-octant maximum on the incremental
-one).  Bar: spins, fired/null counts, M and B bit-exact; clock within 1e-12
+(two colours and the bound on the re-binning kernel and in batches, the
+all-octant maximum on the incremental one).  Bar: spins, fired/null counts, M and B bit-exact; clock within 1e-12
 relative."""
 import numpy as np
 import pytest
@@ -103,29 +103,46 @@ def test_incremental_all_octants(spkmc, L, d, kw):
     assert g.info()["engine"] == spkmc.ENGINES["incremental"]
 
 
+@pytest.mark.parametrize("variant", [TWO, TWO | BOUND])
+@pytest.mark.parametrize("L,d,kw", [
+    (64, 32, dict()),
+    (128, 32, dict(H=0.05)),
+    (64, 16, dict(init="up", rates="metropolis")),
+    (128, 16, dict(T=4.6)),
+])
+def test_persistent_two_colours(spkmc, variant, L, d, kw):
+    """Two colours on the re-binning persistent kernel: four frequency lines per
+    domain, a wait on every neighbour after each colour change."""
+    print("case persistent two colours", variant, L, d, kw, flush=True)
+    g = _compare(spkmc, L, d, "packed", "persistent", variant, **kw)
+    assert g.info()["engine"] == spkmc.ENGINES["persistent"]
+
+
 def test_auto_engine_choice(spkmc):
     pick = lambda v: spkmc.Sim(64, 16, variant=v, seed=1).info()["engine"]  # noqa: E731
     assert pick(0) == spkmc.ENGINES["persistent"]
     assert pick(BOUND) == spkmc.ENGINES["persistent"]
     assert pick(RMAX_ALL) == spkmc.ENGINES["incremental"]
-    assert pick(TWO) == spkmc.ENGINES["cycle"]
-    assert pick(TWO | BOUND) == spkmc.ENGINES["cycle"]
+    assert pick(TWO) == spkmc.ENGINES["persistent"]
+    assert pick(TWO | BOUND) == spkmc.ENGINES["persistent"]
+    assert pick(TWO | RMAX_ALL) == spkmc.ENGINES["cycle"]
     with pytest.raises(spkmc.SpkmcError):
-        spkmc.Sim(64, 16, variant=TWO, engine="persistent", seed=1)
+        spkmc.Sim(64, 16, variant=TWO, engine="incremental", seed=1)
     with pytest.raises(spkmc.SpkmcError):
         spkmc.Sim(64, 16, variant=BOUND, engine="incremental", seed=1)
 
 
-def test_bound_variant_in_a_batch(spkmc):
-    """Batches run the re-binning kernel, so fixed-bound lattices batch too,
-    bit-identical to their solo runs."""
-    specs = [(64, 16, 0.0, 3), (32, 16, 0.05, 4), (128, 16, -0.05, 5)]
+def test_variants_in_one_batch(spkmc):
+    """Batches run the re-binning kernel, so lattices of different variants
+    (contract, bound, two colours, both) share one launch, each bit-identical
+    to its solo run."""
+    specs = [(64, 16, 0.0, 3, 0), (32, 16, 0.05, 4, BOUND), (128, 16, -0.05, 5, TWO), (64, 16, 0.0, 6, TWO | BOUND)]
     solo, batch = [], []
-    for L, d, H, seed in specs:
-        a = spkmc.Sim(L, d, H=H, seed=seed, variant=BOUND, record_cap=64)
+    for L, d, H, seed, v in specs:
+        a = spkmc.Sim(L, d, H=H, seed=seed, variant=v, record_cap=64)
         a.run(60, obs_every=6)
         solo.append((a.state(), a.records(), a.spins().tobytes()))
-        batch.append(spkmc.Sim(L, d, H=H, seed=seed, variant=BOUND, record_cap=64))
+        batch.append(spkmc.Sim(L, d, H=H, seed=seed, variant=v, record_cap=64))
     spkmc.run_batch(batch, 60, obs_every=6)
     for s_, b in zip(solo, batch):
         assert (b.state(), b.records(), b.spins().tobytes()) == s_
