@@ -51,6 +51,7 @@ constexpr int kMaxGrid = 2048;                   // workgroups of one persistent
 constexpr int kMaxWgDomains = 256;               // domains of one workgroup
 constexpr int kRecBanks = 4;                     // record partial banks
 constexpr uint64_t kTimeoutTicks = 200000000ull;  // 2 s of the 100 MHz wall clock
+constexpr uint32_t kNoEvent = 0xFFFFFFFFu;
 
 // Device scratch of the persistent engine (its own region of the state).
 struct PersistScratch {
@@ -95,6 +96,7 @@ __device__ __forceinline__ void flip_word(uint32_t *p, uint32_t m) {
 // v_bitop3: any boolean function of three words; the immediate is its truth
 // table with a = 0xF0, b = 0xCC, c = 0xAA.
 constexpr int kXor3 = 0x96, kMaj3 = 0xE8, kAnd3 = 0x80, kSelAC_BnC = 0xE4;  // (a & c) | (b & ~c)
+constexpr int kXorOr = 0xBE, kXorNor = 0x41;                                // (a ^ b) | c, ~((a ^ b) | c)
 template <int TT>
 __device__ __forceinline__ uint32_t bop(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
@@ -194,22 +196,30 @@ __device__ __forceinline__ void count6(uint32_t a, uint32_t b, uint32_t c, uint3
     o2 = bop<kMaj3>(c1, c2, k0);
 }
 
+// popcount(x) + acc in one v_bcnt (the compiler otherwise counts into zero and
+// sums the counts with extra adds)
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
 // 13 moments: pop(S), pop(b0), pop(b1), pop(b2), pop(b0b1), pop(b0b2), pop(b1b2)
 // and the same six products with S.
 __device__ __forceinline__ void moments(uint32_t S, uint32_t b0, uint32_t b1, uint32_t b2, uint32_t (&m)[13]) {
-    m[0] += __builtin_popcount(S);
-    m[1] += __builtin_popcount(b0);
-    m[2] += __builtin_popcount(b1);
-    m[3] += __builtin_popcount(b2);
-    m[4] += __builtin_popcount(b0 & b1);
-    m[5] += __builtin_popcount(b0 & b2);
-    m[6] += __builtin_popcount(b1 & b2);
-    m[7] += __builtin_popcount(S & b0);
-    m[8] += __builtin_popcount(S & b1);
-    m[9] += __builtin_popcount(S & b2);
-    m[10] += __builtin_popcount(bop<kAnd3>(S, b0, b1));
-    m[11] += __builtin_popcount(bop<kAnd3>(S, b0, b2));
-    m[12] += __builtin_popcount(bop<kAnd3>(S, b1, b2));
+    m[0] = bcnt_acc(S, m[0]);
+    m[1] = bcnt_acc(b0, m[1]);
+    m[2] = bcnt_acc(b1, m[2]);
+    m[3] = bcnt_acc(b2, m[3]);
+    m[4] = bcnt_acc(b0 & b1, m[4]);
+    m[5] = bcnt_acc(b0 & b2, m[5]);
+    m[6] = bcnt_acc(b1 & b2, m[6]);
+    m[7] = bcnt_acc(S & b0, m[7]);
+    m[8] = bcnt_acc(S & b1, m[8]);
+    m[9] = bcnt_acc(S & b2, m[9]);
+    m[10] = bcnt_acc(bop<kAnd3>(S, b0, b1), m[10]);
+    m[11] = bcnt_acc(bop<kAnd3>(S, b0, b2), m[11]);
+    m[12] = bcnt_acc(bop<kAnd3>(S, b1, b2), m[12]);
 }
 
 // Histogram (class c = 7 [s = +1] + a) from the moments of an octant of n sites.
@@ -489,8 +499,8 @@ struct PersistShared {
     double rk[kMaxWgDomains];
     uint32_t zbuf[64][24];             // per row: z face words below (8), above (8), zeros (8)
     uint32_t nbdom[kMaxWgDomains][6];  // per domain: the neighbour domains -x, +x, -y, +y, -z, +z
-    uint32_t flipq[kMaxWgDomains];     // flips of this cycle: (domain << 16) | (class << 12) | site q
-    uint32_t nflip;
+    uint32_t selq[kMaxWgDomains];      // per row: (class << 12) | site q of its event, or kNoEvent
+    double rpred[8];                   // per colour: the last R_max seen (the prediction)
     double rmax;
     int abort;
     uint32_t nbr_bits[6][kMaxGrid / 32];  // neighbour workgroups per direction, as a bitmap
@@ -635,6 +645,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         sh.abort = 0;
         sh.pend_head = sh.pend_tail = 0;
     }
+    if (tid < 8) sh.rpred[tid] = 0.0;  // no prediction yet
     if (tid < 14) sh.r[tid] = g.r[tid];
     if (l < 8) sh.zbuf[row][16 + l] = 0;
     for (uint32_t i = tid; i < nvalid * 6; i += nthr) {
@@ -822,6 +833,84 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                 compute_octant<H, false>(raw[pp & 1], valid, l, sh.zbuf[row], pl[pp], m);
             }
         }
+        // --- steps 3, 4 and 4b: event or null in every line.  The selection runs
+        // first on a predicted R_max (the last one seen for this colour) while the
+        // other workgroups' maxima travel; once the true R_max is known every row
+        // re-derives its class with one ballot and selects again only if the class
+        // changed, so the outcome is exactly that of the true R_max.
+        // lane pp of each row draws for the row's line of pass pp
+        U4 dw;
+        {
+            const uint32_t kd = kbase + (uint32_t)((l < P ? l : 0) * rows + row);
+            dw = philox10((uint32_t)n, (uint32_t)(n >> 32), line_dom(kd), (uint32_t)line_oct(kd, s), g.seed);
+        }
+        constexpr int WPL = Planes<H>::W;
+        // one row's class for a target: lane c of the row tests class c (-1: null)
+        auto row_class = [&](uint32_t ld, bool valid, double target) -> int {
+            const bool hit = valid && l < 14 && target < sh.acc[ld][l < 14 ? l : 13];
+            const uint64_t bal = __ballot(hit);
+            const uint32_t rowbits = (uint32_t)(bal >> (16 * (row & 3))) & 0xFFFFu;
+            return rowbits ? __builtin_ctz(rowbits) : -1;
+        };
+        // the event of pass pp's row for class cs: the j-th site of the class in
+        // canonical order, into the row's selection slot
+        auto select_site = [&](int pp, uint32_t ld, int cs, uint32_t uz) {
+            if (l == 0) sh.selq[ld] = kNoEvent;
+            uint32_t ncs = 0;
+            if (cs >= 0) ncs = INC ? hcount(sh.histp[ld][s], cs) : sh.hist[ld][cs];
+            const uint32_t j = cs >= 0 ? mul_index(uz, ncs) : 0u;
+            // class cs as (spin, n_up pattern): up spin (cs >= 7): n_up = cs - 7; down
+            // spin: n_up = 6 - cs.  A row without an event never uses its masks.
+            const int up = cs >= 7, v = up ? cs - 7 : 6 - cs;
+            const uint32_t ps = up ? 0xFFFFFFFFu : 0u;  // the pattern each plane must equal
+            const uint32_t p0 = (v & 1) ? 0xFFFFFFFFu : 0u, p1 = (v & 2) ? 0xFFFFFFFFu : 0u;
+            const uint32_t p2 = (v & 4) ? 0xFFFFFFFFu : 0u;
+            uint32_t mk[WPL];
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int p = 0; p < WPL; ++p) {
+                // sites of class cs: no plane differs from its pattern; (a ^ b) | c per step
+                uint32_t d = pl[pp].S[p] ^ ps;
+                d = bop<kXorOr>(pl[pp].b0[p], p0, d);
+                d = bop<kXorOr>(pl[pp].b1[p], p1, d);
+                mk[p] = bop<kXorNor>(pl[pp].b2[p], p2, d);
+                cnt = bcnt_acc(mk[p], cnt);
+            }
+            // inclusive prefix over the 16 lanes of the row (canonical order = lane order)
+            const uint32_t incl = row_scan(cnt);
+            const uint32_t excl = incl - cnt;
+            if (cs >= 0 && j >= excl && j < incl) {
+                uint32_t r = j - excl, msk = 0;
+                int wsel = WPL;
+#pragma unroll
+                for (int p = 0; p < WPL; ++p) {
+                    uint32_t c = __builtin_popcount(mk[p]);
+                    if (wsel == WPL) {
+                        if (r < c) { wsel = p; msk = mk[p]; }
+                        else r -= c;
+                    }
+                }
+                if (wsel == WPL || msk == 0) {  // counts disagree with masks: report, flip nothing
+                    atomicOr(&st->error, kErrSelect);
+                } else {
+                    const uint32_t q = (uint32_t)(l * WPL + wsel) * 32 + (uint32_t)nth_set_bit(msk, r);
+                    sh.selq[ld] = ((uint32_t)cs << 12) | q;  // after lane 0's store, same wavefront
+                }
+            }
+        };
+        uint32_t cpred = 0;  // per pass: predicted class + 1, five bits each
+        {
+            const double Rspec = bound ? g.rbound : sh.rpred[s];
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                const uint32_t ld = (uint32_t)(pp * rows + row);
+                const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
+                const int cs = row_class(ld, ld < nvalid, unit53(ux, uy) * Rspec);
+                cpred |= (uint32_t)(cs + 1) << (5 * pp);
+                select_site(pp, ld, cs, uz);
+            }
+        }
+
         if (tid < 64 && !bound) {
             // workgroup 0 sums a record stored two or more cycles ago while it waits
             if (recorder && sh.pend_head != sh.pend_tail && sh.pend_cycle[sh.pend_head % kRecBanks] + 2 <= n + 1)
@@ -866,78 +955,29 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         if (sh.abort) break;
         const double Rmax = bound ? g.rbound : sh.rmax;
 
-        // --- steps 3, 4 and 4b: event or null in every domain
-        if (tid == 0) sh.nflip = 0;
-        // lane pp of each row draws for the row's domain of pass pp
-        U4 dw;
-        {
-            const uint32_t kd = kbase + (uint32_t)((l < P ? l : 0) * rows + row);
-            dw = philox10((uint32_t)n, (uint32_t)(n >> 32), line_dom(kd), (uint32_t)line_oct(kd, s), g.seed);
-        }
-        __syncthreads();
+        if (!bound) {
+            // the true R_max: rows whose class differs select again
+            if (tid == 0) sh.rpred[s] = Rmax;
 #pragma unroll
-        for (int pp = 0; pp < P; ++pp) {
-            const uint32_t ld = (uint32_t)(pp * rows + row);
-            const bool valid = ld < nvalid;
-            const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
-            const double target = unit53(ux, uy) * Rmax;
-            // first class whose running sum exceeds the target (lane c of the row
-            // tests class c); none: the null event
-            const bool hit = valid && l < 14 && target < sh.acc[ld][l < 14 ? l : 13];
-            const uint64_t bal = __ballot(hit);
-            const uint32_t rowbits = (uint32_t)(bal >> (16 * (row & 3))) & 0xFFFFu;
-            const int cs = rowbits ? __builtin_ctz(rowbits) : -1;
-            uint32_t ncs = 0;
-            if (cs >= 0) ncs = INC ? hcount(sh.histp[ld][s], cs) : sh.hist[ld][cs];
-            const uint32_t j = cs >= 0 ? mul_index(uz, ncs) : 0u;
-            // class cs as (spin, n_up pattern): up spin: n_up = a; down spin: n_up = 6 - a
-            const int up = cs >= 7, aa = cs >= 0 ? cs % 7 : 0, v = up ? aa : 6 - aa;
-            const uint32_t es = up ? 0u : 0xFFFFFFFFu;  // bits that must be 0 after the xor
-            const uint32_t e0 = (v & 1) ? 0u : 0xFFFFFFFFu, e1 = (v & 2) ? 0u : 0xFFFFFFFFu;
-            const uint32_t e2 = (v & 4) ? 0u : 0xFFFFFFFFu;
-            constexpr int WPL = Planes<H>::W;
-            uint32_t mk[WPL];
-            uint32_t cnt = 0;
-#pragma unroll
-            for (int p = 0; p < WPL; ++p) {
-                // sites of class cs: every plane equal to the class pattern
-                uint32_t m2 = bop<kAnd3>(pl[pp].S[p] ^ es, pl[pp].b0[p] ^ e0, pl[pp].b1[p] ^ e1);
-                mk[p] = cs >= 0 ? (m2 & (pl[pp].b2[p] ^ e2)) : 0u;
-                cnt += __builtin_popcount(mk[p]);
-            }
-            // inclusive prefix over the 16 lanes of the row (canonical order = lane order)
-            const uint32_t incl = row_scan(cnt);
-            const uint32_t excl = incl - cnt;
-            if (cs >= 0 && j >= excl && j < incl) {
-                uint32_t r = j - excl, msk = 0;
-                int wsel = WPL;
-#pragma unroll
-                for (int p = 0; p < WPL; ++p) {
-                    uint32_t c = __builtin_popcount(mk[p]);
-                    if (wsel == WPL) {
-                        if (r < c) { wsel = p; msk = mk[p]; }
-                        else r -= c;
-                    }
-                }
-                if (wsel == WPL || msk == 0) {  // counts disagree with masks: report, flip nothing
-                    atomicOr(&st->error, kErrSelect);
-                } else {
-                    const uint32_t q = (uint32_t)(l * WPL + wsel) * 32 + (uint32_t)nth_set_bit(msk, r);
-                    const uint32_t slot = atomicAdd(&sh.nflip, 1u);
-                    sh.flipq[slot] = (ld << 16) | ((uint32_t)cs << 12) | q;
-                }
+            for (int pp = 0; pp < P; ++pp) {
+                const uint32_t ld = (uint32_t)(pp * rows + row);
+                const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
+                const int cs = row_class(ld, ld < nvalid, unit53(ux, uy) * Rmax);
+                if ((uint32_t)(cs + 1) != ((cpred >> (5 * pp)) & 31u)) select_site(pp, ld, cs, uz);
             }
         }
         __syncthreads();
         // --- the flips of this cycle
-        // incremental engine: three threads per flip, one per axis, each moving the
+        // one thread per row with an event; incremental engine: three threads per
+        // such row, one per axis, each moving the
         // classes of the flipped site's two neighbours along its axis; the first
         // also flips the site (spin word and face copies) and moves its class
-        const uint32_t nwork = INC ? 3 * sh.nflip : sh.nflip;
+        const uint32_t nwork = INC ? 3 * D : D;
         for (uint32_t t = tid; t < nwork; t += nthr) {
-            const uint32_t i = INC ? t / 3 : t, ax = INC ? t % 3 : 0;
-            const uint32_t f = sh.flipq[i];
-            const uint32_t ld = f >> 16, cs = (f >> 12) & 15u, q = f & 0xFFFu;
+            const uint32_t ld = INC ? t / 3 : t, ax = INC ? t % 3 : 0;
+            const uint32_t f = sh.selq[ld];
+            if (f == kNoEvent) continue;
+            const uint32_t cs = f >> 12, q = f & 0xFFFu;
             const uint32_t k = line_dom(kbase + ld);
             const int so = line_oct(kbase + ld, s);  // the line's octant
             if constexpr (INC) {
