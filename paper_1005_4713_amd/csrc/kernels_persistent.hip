@@ -89,6 +89,13 @@ __device__ __forceinline__ void st64(uint64_t *p, uint64_t v) {
 __device__ __forceinline__ uint64_t ld_words2(const uint32_t *p) {  // two consecutive words, 8-byte aligned
     return ld64(reinterpret_cast<const uint64_t *>(p));
 }
+// Buffer view of the packed spins (byte offsets below 2^31 for every supported
+// size; the hardware returns 0 past the end), and the cache policy of a
+// device-coherent load (sc1).
+constexpr int kCoherent = 16;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t spins_rsrc(const Geom &g) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)g.A, (short)0, (int)(g.N / 8u), 0x00020000);
+}
 __device__ __forceinline__ void flip_word(uint32_t *p, uint32_t m) {
     (void)__hip_atomic_fetch_xor(p, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -264,26 +271,41 @@ struct Raw<8> {
 
 // --- h = 16 --------------------------------------------------------------------
 // lane l = plane lz; word p holds rows ly = 2p (bits 0..15) and 2p + 1 (bits 16..31).
-__device__ __forceinline__ void load16(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb, Raw<16> &r) {
+__device__ __forceinline__ void load16_words(const Geom &g, uint32_t k, int s, bool valid, int l, Raw<16> &r) {
 #pragma unroll
     for (int p = 0; p < 8; ++p) r.W[p] = 0;
-    r.xm = r.xp = r.ym = r.yp = r.zw = 0;
     if (!valid) return;
+    // the lane's 32 contiguous bytes in two 16-byte device-coherent loads
     const uint32_t a0 = (k * 8u + (uint32_t)s) * 128u + (uint32_t)l * 8u;  // word index, < N / 32
+    const __amdgpu_buffer_rsrc_t rs = spins_rsrc(g);
 #pragma unroll
-    for (int p = 0; p < 8; p += 2) {
-        uint64_t v = ld_words2(&g.A[a0 + p]);
-        r.W[p] = (uint32_t)v;
-        r.W[p + 1] = (uint32_t)(v >> 32);
+    for (int p = 0; p < 8; p += 4) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)((a0 + (uint32_t)p) * 4u), 0, kCoherent);
+        r.W[p] = v[0];
+        r.W[p + 1] = v[1];
+        r.W[p + 2] = v[2];
+        r.W[p + 3] = v[3];
     }
+}
+// the halo words of the axes in the mask `axes` (bit a: axis a)
+__device__ __forceinline__ void load16_faces(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
+                                             int axes, Raw<16> &r) {
+    if (axes & 1) r.xm = r.xp = 0;
+    if (axes & 2) r.ym = r.yp = 0;
+    if (axes & 4) r.zw = 0;
+    if (!valid) return;
     HaloFaces hf = halo_faces(g, k, s, nb);
     // x faces: bit ly + 16 lz -> half-word l; y faces: bit lx + 16 lz -> half-word l
-    r.xm = ld32(&g.F[hf.lo[0] + (l >> 1)]);
-    r.xp = ld32(&g.F[hf.hi[0] + (l >> 1)]);
-    r.ym = ld32(&g.F[hf.lo[1] + (l >> 1)]);
-    r.yp = ld32(&g.F[hf.hi[1] + (l >> 1)]);
+    if (axes & 1) {
+        r.xm = ld32(&g.F[hf.lo[0] + (l >> 1)]);
+        r.xp = ld32(&g.F[hf.hi[0] + (l >> 1)]);
+    }
+    if (axes & 2) {
+        r.ym = ld32(&g.F[hf.lo[1] + (l >> 1)]);
+        r.yp = ld32(&g.F[hf.hi[1] + (l >> 1)]);
+    }
     // z faces (bit lx + 16 ly, the layout of a plane), one word per lane
-    r.zw = ld32(&g.F[(l < 8 ? hf.lo[2] : hf.hi[2]) + (l & 7)]);
+    if (axes & 4) r.zw = ld32(&g.F[(l < 8 ? hf.lo[2] : hf.hi[2]) + (l & 7)]);
 }
 
 // zrow: this row's 24 LDS words: face below (8), face above (8), zeros (8).
@@ -323,21 +345,30 @@ __device__ __forceinline__ void compute16(const Raw<16> &r, bool valid, int l, u
 __device__ __forceinline__ uint32_t spread4(uint32_t nib) {  // bits 0..3 -> bits 0, 8, 16, 24
     return (nib * 0x00204081u) & 0x01010101u;
 }
-__device__ __forceinline__ void load8(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb, Raw<8> &r) {
-    int lz = l >> 1, p = l & 1;
-    r.w = r.xm = r.xp = r.yface = r.zface = 0;
+__device__ __forceinline__ void load8_words(const Geom &g, uint32_t k, int s, bool valid, int l, Raw<8> &r) {
+    r.w = valid ? ld32(&g.A[(k * 8u + (uint32_t)s) * 16u + (uint32_t)l]) : 0u;
+}
+__device__ __forceinline__ void load8_faces(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
+                                            int axes, Raw<8> &r) {
+    const int lz = l >> 1, p = l & 1;
+    if (axes & 1) r.xm = r.xp = 0;
+    if (axes & 2) r.yface = 0;
+    if (axes & 4) r.zface = 0;
     if (!valid) return;
-    r.w = ld32(&g.A[(k * 8u + (uint32_t)s) * 16u + (uint32_t)l]);
     HaloFaces hf = halo_faces(g, k, s, nb);
     // x faces: bit ly + 8 lz; rows 4p..4p+3 of plane lz = bits 4l .. 4l + 3
-    r.xm = ld32(&g.F[hf.lo[0] + (l >> 3)]);
-    r.xp = ld32(&g.F[hf.hi[0] + (l >> 3)]);
+    if (axes & 1) {
+        r.xm = ld32(&g.F[hf.lo[0] + (l >> 3)]);
+        r.xp = ld32(&g.F[hf.hi[0] + (l >> 3)]);
+    }
     // y faces: bit lx + 8 lz = byte lz; the lowest row of p = 0 needs the face below,
     // the highest row of p = 1 the face above
-    r.yface = ld32(&g.F[(p == 0 ? hf.lo[1] : hf.hi[1]) + (lz >> 2)]);
+    if (axes & 2) r.yface = ld32(&g.F[(p == 0 ? hf.lo[1] : hf.hi[1]) + (lz >> 2)]);
     // z faces: bit lx + 8 ly, word p covers rows 4p .. 4p + 3
-    if (lz == 0) r.zface = ld32(&g.F[hf.lo[2] + p]);
-    if (lz == 7) r.zface = ld32(&g.F[hf.hi[2] + p]);
+    if (axes & 4) {
+        if (lz == 0) r.zface = ld32(&g.F[hf.lo[2] + p]);
+        if (lz == 7) r.zface = ld32(&g.F[hf.hi[2] + p]);
+    }
 }
 template <bool MOM>
 __device__ __forceinline__ void compute8(const Raw<8> &r, bool valid, int l, uint32_t *, Planes<8> &P,
@@ -364,10 +395,21 @@ __device__ __forceinline__ void compute8(const Raw<8> &r, bool valid, int l, uin
 }
 
 template <int H>
+__device__ __forceinline__ void load_words(const Geom &g, uint32_t k, int s, bool valid, int l, Raw<H> &r) {
+    if constexpr (H == 16) load16_words(g, k, s, valid, l, r);
+    else load8_words(g, k, s, valid, l, r);
+}
+template <int H>
+__device__ __forceinline__ void load_faces(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
+                                           int axes, Raw<H> &r) {
+    if constexpr (H == 16) load16_faces(g, k, s, valid, l, nb, axes, r);
+    else load8_faces(g, k, s, valid, l, nb, axes, r);
+}
+template <int H>
 __device__ __forceinline__ void load_octant(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
                                             Raw<H> &r) {
-    if constexpr (H == 16) load16(g, k, s, valid, l, nb, r);
-    else load8(g, k, s, valid, l, nb, r);
+    load_words<H>(g, k, s, valid, l, r);
+    load_faces<H>(g, k, s, valid, l, nb, 7, r);
 }
 template <int H, bool MOM>
 __device__ __forceinline__ void compute_octant(const Raw<H> &r, bool valid, int l, uint32_t *zrow, Planes<H> &P,
@@ -482,6 +524,27 @@ __device__ __forceinline__ int nth_set_bit(uint32_t m, uint32_t r) {
         }
     }
     return pos;
+}
+
+// Maximum of a non-negative double over the wavefront, returned in lane 63:
+// DPP shifts within each row (lanes from outside read 0), then the last lane of
+// each row carried into the rows above.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWS, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWS, 0xF, true);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+    v = fmax(v, dpp_f64<kRowShr1, 0xF>(v));
+    v = fmax(v, dpp_f64<kRowShr2, 0xF>(v));
+    v = fmax(v, dpp_f64<kRowShr4, 0xF>(v));
+    v = fmax(v, dpp_f64<kRowShr8, 0xF>(v));
+    v = fmax(v, dpp_f64<kRowBcast15, 0xA>(v));
+    v = fmax(v, dpp_f64<kRowBcast31, 0xC>(v));
+    return v;
 }
 
 // wall clock (100 MHz) for bounded waits
@@ -692,6 +755,10 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     int prev_colour = -1;
     const bool bound = (g.variant & SPKMC_VARIANT_RMAX_BOUND) != 0;   // re-binning engine only
     const bool rmax_all = INC && (g.variant & SPKMC_VARIANT_RMAX_ALL);  // incremental engine only
+    // -ln u of the coming cycle's clock step
+    double lnu = -log(cycle_draw(g.seed, n0, lpd == 4).ut);
+    // the cycle after which the next observation record falls due
+    uint64_t next_rec = obs_every ? (n0 / obs_every + 1) * obs_every : ~0ull;
 
     for (uint64_t n = n0; n < n_end; ++n) {
         CycleDraw cd = cycle_draw(g.seed, n, lpd == 4);
@@ -769,8 +836,10 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
 #pragma unroll
             for (int pp = 0; pp < P; ++pp) {
                 const uint32_t ld = (uint32_t)(pp * rows + row);
-                load_octant<H>(g, line_dom(kbase + ld), line_oct(kbase + ld, s), ld < nvalid, l,
-                               sh.nbdom[ld < nvalid ? ld : 0], raw[pp]);
+                const bool valid = ld < nvalid;
+                const uint32_t k = line_dom(kbase + ld);
+                const int o = line_oct(kbase + ld, s);
+                load_octant<H>(g, k, o, valid, l, sh.nbdom[valid ? ld : 0], raw[pp]);
             }
 #pragma unroll
             for (int pp = 0; pp < P; ++pp) {
@@ -780,11 +849,18 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
 #pragma unroll
                 for (int i = 0; i < 13; ++i) m[i] = 0;
                 compute_octant<H, true>(raw[pp], valid, l, sh.zbuf[row], pl[pp], m);
+                // row totals (at most h^3 <= 4096 each), two to a word for the scan
+                uint32_t mp[7];
 #pragma unroll
-                for (int i = 0; i < 13; ++i) m[i] = row_scan(m[i]);
+                for (int i = 0; i < 6; ++i) mp[i] = row_scan(m[2 * i] | (m[2 * i + 1] << 16));
+                mp[6] = row_scan(m[12]);
                 if (l == 15) {
 #pragma unroll
-                    for (int i = 0; i < 13; ++i) sh.mom[ld][i] = m[i];
+                    for (int i = 0; i < 6; ++i) {
+                        sh.mom[ld][2 * i] = mp[i] & 0xFFFFu;
+                        sh.mom[ld][2 * i + 1] = mp[i] >> 16;
+                    }
+                    sh.mom[ld][12] = mp[6];
                 }
             }
             __syncthreads();
@@ -813,8 +889,8 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         if (tid < 64 && !bound) {
             double v = 0.0;
             for (uint32_t i = tid; i < D; i += 64) v = fmax(v, sh.rk[i]);
-            for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-            if (tid == 0) st64(&bank[gid], double_to_bits(v) | gen);
+            v = wave_max_nonneg(v);
+            if (tid == 63) st64(&bank[gid], double_to_bits(v) | gen);
         }
         if constexpr (INC) {
             // the active octants' class planes, while the other maxima travel
@@ -948,8 +1024,8 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
 #pragma unroll
                 for (int i = 0; i < kSlotsPerLane; ++i) best = fmax(best, bits_to_double(sv[i] & ~(1ull << 63)));
             }
-            for (int o = 32; o > 0; o >>= 1) best = fmax(best, __shfl_xor(best, o));
-            if (tid == 0) sh.rmax = best;
+            best = wave_max_nonneg(best);
+            if (tid == 63) sh.rmax = best;
         }
         __syncthreads();
         if (sh.abort) break;
@@ -1045,18 +1121,25 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             mydB += 12 - 4 * (long long)(cs % 7);  // and its aligned count
         }
 
+        // this thread's flips complete (its only memory operations in flight)
+        __builtin_amdgcn_s_waitcnt(0);
+
+        // the next cycle's words that this cycle's flips leave alone (re-binning
+        // engine): every workgroup has finished the previous cycle (it published
+        // this cycle's maximum, or with the fixed bound the neighbours' flags were
+        // awaited), and only octants of colour s change in this cycle
         // --- step 5: the clock, identical in every workgroup
         {
-            double dt = -log(cd.ut) / ((lpd == 4 ? 2.0 : 8.0) * Rmax);
+            double dt = lnu / ((lpd == 4 ? 2.0 : 8.0) * Rmax);
             t = t + dt;
         }
-
+        lnu = -log(cycle_draw(g.seed, n + 1, lpd == 4).ut);
         // flips complete, then publish them (step 6)
-        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
 
         const bool last = n + 1 == n_end;
-        const bool record = obs_every && ((n + 1) % obs_every) == 0 && g.rec_cap;
+        const bool record = n + 1 == next_rec && g.rec_cap;
+        if (n + 1 == next_rec) next_rec += obs_every;
         if (record || last) {
             // workgroup totals since launch start
             long long F = myF, dM = mydM, dB = mydB;
@@ -1117,7 +1200,10 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             if (record && !last) rec_index += 1;
         }
         if (tid == 0) {
-            __builtin_amdgcn_s_waitcnt(0);
+            // the record partials stored above go out first; the flips are complete
+            // (each thread waited for its own before the barrier), and the loads of
+            // the next cycle's words may stay in flight
+            if (record || last) __builtin_amdgcn_s_waitcnt(0);
             st64(&xs.flag[gid], n + 1);
         }
         if (bound && record && !last) {  // uniform over the workgroup
