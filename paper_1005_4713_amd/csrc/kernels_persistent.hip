@@ -96,6 +96,12 @@ constexpr int kCoherent = 16;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t spins_rsrc(const Geom &g) {
     return __builtin_amdgcn_make_buffer_rsrc((void *)g.A, (short)0, (int)(g.N / 8u), 0x00020000);
 }
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t faces_rsrc(const Geom &g) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)g.F, (short)0, (int)((uint64_t)g.K * 8u * g.fwpo * 4u), 0x00020000);
+}
+__device__ __forceinline__ uint32_t ld_face(__amdgpu_buffer_rsrc_t rs, uint32_t w) {  // word w of the face copies
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(w * 4u), 0, kCoherent);
+}
 __device__ __forceinline__ void flip_word(uint32_t *p, uint32_t m) {
     (void)__hip_atomic_fetch_xor(p, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -295,17 +301,18 @@ __device__ __forceinline__ void load16_faces(const Geom &g, uint32_t k, int s, b
     if (axes & 4) r.zw = 0;
     if (!valid) return;
     HaloFaces hf = halo_faces(g, k, s, nb);
+    const __amdgpu_buffer_rsrc_t rf = faces_rsrc(g);
     // x faces: bit ly + 16 lz -> half-word l; y faces: bit lx + 16 lz -> half-word l
     if (axes & 1) {
-        r.xm = ld32(&g.F[hf.lo[0] + (l >> 1)]);
-        r.xp = ld32(&g.F[hf.hi[0] + (l >> 1)]);
+        r.xm = ld_face(rf, hf.lo[0] + (l >> 1));
+        r.xp = ld_face(rf, hf.hi[0] + (l >> 1));
     }
     if (axes & 2) {
-        r.ym = ld32(&g.F[hf.lo[1] + (l >> 1)]);
-        r.yp = ld32(&g.F[hf.hi[1] + (l >> 1)]);
+        r.ym = ld_face(rf, hf.lo[1] + (l >> 1));
+        r.yp = ld_face(rf, hf.hi[1] + (l >> 1));
     }
     // z faces (bit lx + 16 ly, the layout of a plane), one word per lane
-    if (axes & 4) r.zw = ld32(&g.F[(l < 8 ? hf.lo[2] : hf.hi[2]) + (l & 7)]);
+    if (axes & 4) r.zw = ld_face(rf, (l < 8 ? hf.lo[2] : hf.hi[2]) + (l & 7));
 }
 
 // zrow: this row's 24 LDS words: face below (8), face above (8), zeros (8).
@@ -356,18 +363,19 @@ __device__ __forceinline__ void load8_faces(const Geom &g, uint32_t k, int s, bo
     if (axes & 4) r.zface = 0;
     if (!valid) return;
     HaloFaces hf = halo_faces(g, k, s, nb);
+    const __amdgpu_buffer_rsrc_t rf = faces_rsrc(g);
     // x faces: bit ly + 8 lz; rows 4p..4p+3 of plane lz = bits 4l .. 4l + 3
     if (axes & 1) {
-        r.xm = ld32(&g.F[hf.lo[0] + (l >> 3)]);
-        r.xp = ld32(&g.F[hf.hi[0] + (l >> 3)]);
+        r.xm = ld_face(rf, hf.lo[0] + (l >> 3));
+        r.xp = ld_face(rf, hf.hi[0] + (l >> 3));
     }
     // y faces: bit lx + 8 lz = byte lz; the lowest row of p = 0 needs the face below,
     // the highest row of p = 1 the face above
-    if (axes & 2) r.yface = ld32(&g.F[(p == 0 ? hf.lo[1] : hf.hi[1]) + (lz >> 2)]);
+    if (axes & 2) r.yface = ld_face(rf, (p == 0 ? hf.lo[1] : hf.hi[1]) + (lz >> 2));
     // z faces: bit lx + 8 ly, word p covers rows 4p .. 4p + 3
     if (axes & 4) {
-        if (lz == 0) r.zface = ld32(&g.F[hf.lo[2] + p]);
-        if (lz == 7) r.zface = ld32(&g.F[hf.hi[2] + p]);
+        if (lz == 0) r.zface = ld_face(rf, hf.lo[2] + p);
+        if (lz == 7) r.zface = ld_face(rf, hf.hi[2] + p);
     }
 }
 template <bool MOM>
@@ -678,7 +686,7 @@ __device__ __forceinline__ void bin_all(const Geom &g, uint32_t kbase, uint32_t 
 // neighbours change class, step 6); the active octant is classified only to
 // find the selected site, while the R_max exchange is in flight.
 // INC = false: the active octant of every domain is binned afresh each cycle.
-template <int H, int P, int BLOCK, bool INC>
+template <int H, int P, int BLOCK, bool INC, int LPD>
 __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t gid, PersistShared &sh) {
     const Geom &g = R.g;
     const PersistScratch &xs = R.xs;
@@ -692,7 +700,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     const uint32_t D = (uint32_t)(rows * P);
     // rows run frequency lines: one per domain, or (two colours) the four active
     // octants of each domain, lines 4k .. 4k + 3 of domain k
-    const uint32_t lpd = g.lpd, NL = g.K * lpd;
+    const uint32_t lpd = LPD ? (uint32_t)LPD : g.lpd, NL = g.K * lpd;  // LPD = 0: read at run time
     const uint32_t kbase = gid * D;  // first line of the workgroup
     const uint32_t nvalid = kbase >= NL ? 0u : (NL - kbase < D ? NL - kbase : D);
     auto line_dom = [lpd](uint32_t line) { return lpd == 1 ? line : line >> 2; };
@@ -941,7 +949,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             const uint32_t ps = up ? 0xFFFFFFFFu : 0u;  // the pattern each plane must equal
             const uint32_t p0 = (v & 1) ? 0xFFFFFFFFu : 0u, p1 = (v & 2) ? 0xFFFFFFFFu : 0u;
             const uint32_t p2 = (v & 4) ? 0xFFFFFFFFu : 0u;
-            uint32_t mk[WPL];
+            uint32_t mk[WPL], cum[WPL];
             uint32_t cnt = 0;
 #pragma unroll
             for (int p = 0; p < WPL; ++p) {
@@ -951,29 +959,31 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                 d = bop<kXorOr>(pl[pp].b1[p], p1, d);
                 mk[p] = bop<kXorNor>(pl[pp].b2[p], p2, d);
                 cnt = bcnt_acc(mk[p], cnt);
+                cum[p] = cnt;  // running count over the lane's words
             }
             // inclusive prefix over the 16 lanes of the row (canonical order = lane order)
             const uint32_t incl = row_scan(cnt);
             const uint32_t excl = incl - cnt;
+            if (cs >= 0 && l == 15 && j >= incl) atomicOr(&st->error, kErrSelect);  // counts disagree with masks
             if (cs >= 0 && j >= excl && j < incl) {
-                uint32_t r = j - excl, msk = 0;
-                int wsel = WPL;
+                // the word holding the target: as many words as have running counts not
+                // above its rank; then its rank inside that word
+                const uint32_t r0 = j - excl;
+                uint32_t wsel = 0;
 #pragma unroll
-                for (int p = 0; p < WPL; ++p) {
-                    uint32_t c = __builtin_popcount(mk[p]);
-                    if (wsel == WPL) {
-                        if (r < c) { wsel = p; msk = mk[p]; }
-                        else r -= c;
+                for (int p = 0; p + 1 < WPL; ++p) wsel += cum[p] <= r0 ? 1u : 0u;
+                uint32_t before = 0, msk = mk[0];
+#pragma unroll
+                for (int p = 1; p < WPL; ++p)
+                    if (wsel == (uint32_t)p) {
+                        before = cum[p - 1];
+                        msk = mk[p];
                     }
-                }
-                if (wsel == WPL || msk == 0) {  // counts disagree with masks: report, flip nothing
-                    atomicOr(&st->error, kErrSelect);
-                } else {
-                    const uint32_t q = (uint32_t)(l * WPL + wsel) * 32 + (uint32_t)nth_set_bit(msk, r);
-                    sh.selq[ld] = ((uint32_t)cs << 12) | q;  // after lane 0's store, same wavefront
-                }
+                const uint32_t q = (uint32_t)(l * WPL) * 32 + wsel * 32 + (uint32_t)nth_set_bit(msk, r0 - before);
+                sh.selq[ld] = ((uint32_t)cs << 12) | q;  // after lane 0's store, same wavefront
             }
         };
+
         uint32_t cpred = 0;  // per pass: predicted class + 1, five bits each
         {
             const double Rspec = bound ? g.rbound : sh.rpred[s];
@@ -1272,11 +1282,12 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     }
 }
 
-// One lattice: the descriptor by value.
-template <int H, int P, int BLOCK, bool INC>
+// One lattice: the descriptor by value; LPD, the frequency lines per domain (1
+// or 4), fixed at compile time so that every line of a pass shares its octant.
+template <int H, int P, int BLOCK, bool INC, int LPD>
 __global__ void __launch_bounds__(BLOCK) k_persistent(Replica R) {
     __shared__ PersistShared sh;
-    persistent_body<H, P, BLOCK, INC>(R, blockIdx.x, sh);
+    persistent_body<H, P, BLOCK, INC, LPD>(R, blockIdx.x, sh);
 }
 
 // Many independent lattices in one launch: each workgroup finds its lattice by
@@ -1293,7 +1304,7 @@ __global__ void __launch_bounds__(BLOCK) k_persistent_batch(const Replica *__res
     // the index is the same in every lane: keep the descriptor in scalar registers
     const Replica &R = reps[__builtin_amdgcn_readfirstlane(lo)];
     if (blockIdx.x >= R.first_wg + R.G) return;  // a spare workgroup past the last lattice
-    persistent_body<H, P, BLOCK, INC>(R, blockIdx.x - R.first_wg, sh);
+    persistent_body<H, P, BLOCK, INC, 0>(R, blockIdx.x - R.first_wg, sh);  // lattices of either line count
 }
 
 // Before a launch: slots carry the generation of no cycle of this launch yet,
@@ -1332,26 +1343,33 @@ int persist_rows(int h, bool) { return h == 8 ? 64 : 32; }
 int persist_max_passes(int, bool) { return 4; }
 
 template <int H, int P, int BLOCK>
-static void *kernel_of(bool batch, bool inc) {
-    if (inc) return reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, true>);
-    return batch ? reinterpret_cast<void *>(&k_persistent_batch<H, P, BLOCK, false>)
-                 : reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false>);
+static void *kernel_of(bool batch, bool inc, uint32_t lpd) {
+    if (inc) return reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, true, 1>);
+    if (batch) return reinterpret_cast<void *>(&k_persistent_batch<H, P, BLOCK, false>);
+    return lpd == 4 ? reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false, 4>)
+                    : reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false, 1>);
 }
-// Batches use the re-binning kernel.
-static void *select_kernel(int h, int P, int block, bool batch = false, bool inc = false) {
+// Batches use the re-binning kernel (lines per domain read at run time).
+static void *select_kernel(int h, int P, int block, bool batch = false, bool inc = false, uint32_t lpd = 1) {
     if (batch && inc) return nullptr;
     if (h == 16 && block == 512)
-        return P == 1 ? kernel_of<16, 1, 512>(batch, inc) : P == 2 ? kernel_of<16, 2, 512>(batch, inc)
-               : P == 4 ? kernel_of<16, 4, 512>(batch, inc) : nullptr;
+        return P == 1   ? kernel_of<16, 1, 512>(batch, inc, lpd)
+               : P == 2 ? kernel_of<16, 2, 512>(batch, inc, lpd)
+               : P == 4 ? kernel_of<16, 4, 512>(batch, inc, lpd)
+                        : nullptr;
     if (h == 8 && block == 1024)
-        return P == 1 ? kernel_of<8, 1, 1024>(batch, inc) : P == 2 ? kernel_of<8, 2, 1024>(batch, inc)
-               : P == 4 ? kernel_of<8, 4, 1024>(batch, inc) : nullptr;
+        return P == 1   ? kernel_of<8, 1, 1024>(batch, inc, lpd)
+               : P == 2 ? kernel_of<8, 2, 1024>(batch, inc, lpd)
+               : P == 4 ? kernel_of<8, 4, 1024>(batch, inc, lpd)
+                        : nullptr;
     return nullptr;
 }
 
 bool persistent_supported(const Geom &g, const spkmc_params &p, bool inc, std::string &why) {
     if (g.layout != SPKMC_LAYOUT_PACKED) { why = "needs the PACKED layout"; return false; }
     if (g.h != 8 && g.h != 16) { why = "needs an octant edge of 8 or 16 (domain 16 or 32)"; return false; }
+    // spins and face copies are read through buffer views with 32-bit byte offsets
+    if (g.N / 8 >= (1ull << 31)) { why = "needs fewer than 2^34 sites"; return false; }
     const uint32_t ok = inc ? SPKMC_VARIANT_RMAX_ALL : (SPKMC_VARIANT_RMAX_BOUND | SPKMC_VARIANT_TWO_COLOURS);
     if (p.variant & ~ok) {
         why = inc ? "the incremental engine runs variants 0 and RMAX_ALL"
@@ -1382,7 +1400,7 @@ hipError_t persistent_configure(const Geom &g, const spkmc_params &p, bool inc, 
     // requested domains per workgroup)
     for (int P = 1; P <= pmax; P <<= 1) {
         if (p.wg_domains && p.wg_domains != rows * P) continue;
-        void *kern = select_kernel(g.h, P, block, false, inc);
+        void *kern = select_kernel(g.h, P, block, false, inc, g.lpd);
         if (!kern) return hipErrorInvalidValue;
         int occ = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, 0);
@@ -1412,7 +1430,7 @@ hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint3
                              int wg_domains, bool inc, hipStream_t stream) {
     PersistScratch xs = scratch_of(g, grid);
     int P = wg_domains / (block / 16);
-    void *kern = select_kernel(g.h, P, block, false, inc);
+    void *kern = select_kernel(g.h, P, block, false, inc, g.lpd);
     if (!kern) return hipErrorInvalidValue;
     const uint64_t ndh = inc ? (uint64_t)g.K * 16 : 0;
     uint64_t blocks = ((uint64_t)grid + 255) / 256, bdh = (ndh + 255) / 256;
