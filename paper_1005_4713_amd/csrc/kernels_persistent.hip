@@ -89,18 +89,27 @@ __device__ __forceinline__ void st64(uint64_t *p, uint64_t v) {
 __device__ __forceinline__ uint64_t ld_words2(const uint32_t *p) {  // two consecutive words, 8-byte aligned
     return ld64(reinterpret_cast<const uint64_t *>(p));
 }
-// Buffer view of the packed spins (byte offsets below 2^31 for every supported
-// size; the hardware returns 0 past the end), and the cache policy of a
-// device-coherent load (sc1).
+// Buffer views of the packed spins and of the face copies (byte offsets below
+// 2^31 for every size the persistent engine takes), and the cache policy of a
+// device-coherent load (sc1).  A load at an offset past the end returns 0: the
+// rows of a pass without a line load there, so that every pass issues the same
+// loads, unconditionally, and the wait for a pass's words counts only the loads
+// issued after them.
 constexpr int kCoherent = 16;
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t spins_rsrc(const Geom &g) {
-    return __builtin_amdgcn_make_buffer_rsrc((void *)g.A, (short)0, (int)(g.N / 8u), 0x00020000);
+struct Views {
+    __amdgpu_buffer_rsrc_t A, F;
+    int endA, endF;  // sizes in bytes: the offsets that read 0
+};
+__device__ __forceinline__ Views views_of(const Geom &g) {
+    Views v;
+    v.endA = (int)(g.N / 8u);
+    v.endF = (int)((uint64_t)g.K * 8u * g.fwpo * 4u);
+    v.A = __builtin_amdgcn_make_buffer_rsrc((void *)g.A, (short)0, v.endA, 0x00020000);
+    v.F = __builtin_amdgcn_make_buffer_rsrc((void *)g.F, (short)0, v.endF, 0x00020000);
+    return v;
 }
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t faces_rsrc(const Geom &g) {
-    return __builtin_amdgcn_make_buffer_rsrc((void *)g.F, (short)0, (int)((uint64_t)g.K * 8u * g.fwpo * 4u), 0x00020000);
-}
-__device__ __forceinline__ uint32_t ld_face(__amdgpu_buffer_rsrc_t rs, uint32_t w) {  // word w of the face copies
-    return __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(w * 4u), 0, kCoherent);
+__device__ __forceinline__ uint32_t ld_face(const Views &v, bool valid, uint32_t w) {  // word w of the face copies
+    return __builtin_amdgcn_raw_buffer_load_b32(v.F, valid ? (int)(w * 4u) : v.endF, 0, kCoherent);
 }
 __device__ __forceinline__ void flip_word(uint32_t *p, uint32_t m) {
     (void)__hip_atomic_fetch_xor(p, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -278,15 +287,13 @@ struct Raw<8> {
 // --- h = 16 --------------------------------------------------------------------
 // lane l = plane lz; word p holds rows ly = 2p (bits 0..15) and 2p + 1 (bits 16..31).
 __device__ __forceinline__ void load16_words(const Geom &g, uint32_t k, int s, bool valid, int l, Raw<16> &r) {
-#pragma unroll
-    for (int p = 0; p < 8; ++p) r.W[p] = 0;
-    if (!valid) return;
     // the lane's 32 contiguous bytes in two 16-byte device-coherent loads
     const uint32_t a0 = (k * 8u + (uint32_t)s) * 128u + (uint32_t)l * 8u;  // word index, < N / 32
-    const __amdgpu_buffer_rsrc_t rs = spins_rsrc(g);
+    const Views vw = views_of(g);
 #pragma unroll
     for (int p = 0; p < 8; p += 4) {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)((a0 + (uint32_t)p) * 4u), 0, kCoherent);
+        const int off = valid ? (int)((a0 + (uint32_t)p) * 4u) : vw.endA;
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(vw.A, off, 0, kCoherent);
         r.W[p] = v[0];
         r.W[p + 1] = v[1];
         r.W[p + 2] = v[2];
@@ -296,23 +303,19 @@ __device__ __forceinline__ void load16_words(const Geom &g, uint32_t k, int s, b
 // the halo words of the axes in the mask `axes` (bit a: axis a)
 __device__ __forceinline__ void load16_faces(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
                                              int axes, Raw<16> &r) {
-    if (axes & 1) r.xm = r.xp = 0;
-    if (axes & 2) r.ym = r.yp = 0;
-    if (axes & 4) r.zw = 0;
-    if (!valid) return;
-    HaloFaces hf = halo_faces(g, k, s, nb);
-    const __amdgpu_buffer_rsrc_t rf = faces_rsrc(g);
+    const HaloFaces hf = halo_faces(g, k, s, nb);
+    const Views vw = views_of(g);
     // x faces: bit ly + 16 lz -> half-word l; y faces: bit lx + 16 lz -> half-word l
     if (axes & 1) {
-        r.xm = ld_face(rf, hf.lo[0] + (l >> 1));
-        r.xp = ld_face(rf, hf.hi[0] + (l >> 1));
+        r.xm = ld_face(vw, valid, hf.lo[0] + (l >> 1));
+        r.xp = ld_face(vw, valid, hf.hi[0] + (l >> 1));
     }
     if (axes & 2) {
-        r.ym = ld_face(rf, hf.lo[1] + (l >> 1));
-        r.yp = ld_face(rf, hf.hi[1] + (l >> 1));
+        r.ym = ld_face(vw, valid, hf.lo[1] + (l >> 1));
+        r.yp = ld_face(vw, valid, hf.hi[1] + (l >> 1));
     }
     // z faces (bit lx + 16 ly, the layout of a plane), one word per lane
-    if (axes & 4) r.zw = ld_face(rf, (l < 8 ? hf.lo[2] : hf.hi[2]) + (l & 7));
+    if (axes & 4) r.zw = ld_face(vw, valid, (l < 8 ? hf.lo[2] : hf.hi[2]) + (l & 7));
 }
 
 // zrow: this row's 24 LDS words: face below (8), face above (8), zeros (8).
@@ -353,31 +356,27 @@ __device__ __forceinline__ uint32_t spread4(uint32_t nib) {  // bits 0..3 -> bit
     return (nib * 0x00204081u) & 0x01010101u;
 }
 __device__ __forceinline__ void load8_words(const Geom &g, uint32_t k, int s, bool valid, int l, Raw<8> &r) {
-    r.w = valid ? ld32(&g.A[(k * 8u + (uint32_t)s) * 16u + (uint32_t)l]) : 0u;
+    const Views vw = views_of(g);
+    const int off = valid ? (int)(((k * 8u + (uint32_t)s) * 16u + (uint32_t)l) * 4u) : vw.endA;
+    r.w = __builtin_amdgcn_raw_buffer_load_b32(vw.A, off, 0, kCoherent);
 }
 __device__ __forceinline__ void load8_faces(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
                                             int axes, Raw<8> &r) {
     const int lz = l >> 1, p = l & 1;
-    if (axes & 1) r.xm = r.xp = 0;
-    if (axes & 2) r.yface = 0;
-    if (axes & 4) r.zface = 0;
-    if (!valid) return;
-    HaloFaces hf = halo_faces(g, k, s, nb);
-    const __amdgpu_buffer_rsrc_t rf = faces_rsrc(g);
+    const HaloFaces hf = halo_faces(g, k, s, nb);
+    const Views vw = views_of(g);
     // x faces: bit ly + 8 lz; rows 4p..4p+3 of plane lz = bits 4l .. 4l + 3
     if (axes & 1) {
-        r.xm = ld_face(rf, hf.lo[0] + (l >> 3));
-        r.xp = ld_face(rf, hf.hi[0] + (l >> 3));
+        r.xm = ld_face(vw, valid, hf.lo[0] + (l >> 3));
+        r.xp = ld_face(vw, valid, hf.hi[0] + (l >> 3));
     }
     // y faces: bit lx + 8 lz = byte lz; the lowest row of p = 0 needs the face below,
     // the highest row of p = 1 the face above
-    if (axes & 2) r.yface = ld_face(rf, (p == 0 ? hf.lo[1] : hf.hi[1]) + (lz >> 2));
-    // z faces: bit lx + 8 ly, word p covers rows 4p .. 4p + 3
-    if (axes & 4) {
-        if (lz == 0) r.zface = ld_face(rf, hf.lo[2] + p);
-        if (lz == 7) r.zface = ld_face(rf, hf.hi[2] + p);
-    }
+    if (axes & 2) r.yface = ld_face(vw, valid, (p == 0 ? hf.lo[1] : hf.hi[1]) + (lz >> 2));
+    // z faces: bit lx + 8 ly, word p covers rows 4p .. 4p + 3; the inner planes read 0
+    if (axes & 4) r.zface = ld_face(vw, valid && (lz == 0 || lz == 7), (lz == 0 ? hf.lo[2] : hf.hi[2]) + p);
 }
+
 template <bool MOM>
 __device__ __forceinline__ void compute8(const Raw<8> &r, bool valid, int l, uint32_t *, Planes<8> &P,
                                          uint32_t (&m)[13]) {
