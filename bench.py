@@ -351,9 +351,10 @@ def main():
     bytes_cycle = info["bytes_per_cycle"]
     launches = 1 if info["engine"] in (spkmc.ENGINES["persistent"], spkmc.ENGINES["incremental"]) else 3 * args.steps
     achieved = bytes_cycle * args.steps / secs / 1e9
+    inc = info["engine"] == spkmc.ENGINES["incremental"]
+    lpd = 4 if sim.params.variant & spkmc.VARIANTS["two_colours"] else 1
     kernel = (f"k_persistent<{info['h']}, {info['wg_domains'] * 16 // info['block']}, {info['block']}, "
-              f"{str(info['engine'] == spkmc.ENGINES['incremental']).lower()}>" if launches == 1
-              else "whole cycle (3 launches)")
+              f"{str(inc).lower()}, {lpd}>" if launches == 1 else "whole cycle (3 launches)")
     traffic, traffic_rec = (None, None)
     if launches == 1:
         traffic, traffic_rec = measured_traffic(w["name"], kernel, args.variant or "contract", args.steps)
