@@ -1133,10 +1133,6 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         // this thread's flips complete (its only memory operations in flight)
         __builtin_amdgcn_s_waitcnt(0);
 
-        // the next cycle's words that this cycle's flips leave alone (re-binning
-        // engine): every workgroup has finished the previous cycle (it published
-        // this cycle's maximum, or with the fixed bound the neighbours' flags were
-        // awaited), and only octants of colour s change in this cycle
         // --- step 5: the clock, identical in every workgroup
         {
             double dt = lnu / ((lpd == 4 ? 2.0 : 8.0) * Rmax);
@@ -1210,8 +1206,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         }
         if (tid == 0) {
             // the record partials stored above go out first; the flips are complete
-            // (each thread waited for its own before the barrier), and the loads of
-            // the next cycle's words may stay in flight
+            // (each thread waited for its own before the barrier)
             if (record || last) __builtin_amdgcn_s_waitcnt(0);
             st64(&xs.flag[gid], n + 1);
         }
