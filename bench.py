@@ -95,6 +95,28 @@ def measured_traffic(workload_name, kernel, variant, steps):
     return None, None
 
 
+def measured_valu(workload_name, kernel):
+    """Vector-issue counters of this kernel and workload from the committed
+    rocprofv3 SQ_INSTS_VALU / SQ_ACTIVE_INST_VALU summary; None if there is none
+    or the kernel source changed since they were taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_valu.json")):
+        with open(path) as f:
+            rec = json.load(f)
+        if rec.get("workload") != workload_name or rec.get("kernel") != kernel:
+            continue
+        m = hashlib.sha256()
+        for name in rec["source_files"]:
+            with open(os.path.join(ROOT, name), "rb") as f:
+                m.update(f.read())
+        if m.hexdigest()[:16] != rec["source_hash"]:
+            return None
+        return {"busy": rec["valu_busy"], "insts_per_wave_cycle": rec["valu_insts_per_wave_cycle"],
+                "source": os.path.relpath(path, ROOT)}
+    return None
+
+
 def cpu_baseline(w, cycles):
     """The oracle as it stands, single-threaded, on a bounded sample of the
     workload: `cycles` spkMC cycles of the full lattice (initialisation not timed)."""
@@ -386,7 +408,8 @@ def main():
                      "kernel": kernel,
                      "bytes_per_cycle": bytes_cycle, "launches": launches,
                      "avg_launch_ms": gpu_ms / launches,
-                     "traffic_source": None if traffic is None else traffic_rec["path"]},
+                     "traffic_source": None if traffic is None else traffic_rec["path"],
+                     "valu": measured_valu(w["name"], kernel) if launches == 1 and not args.variant else None},
     }
     if not args.no_cpu_baseline:
         cyc = args.cpu_cycles or (12 if w["L"] >= 1024 else 80 if w["L"] >= 512 else 4000)
