@@ -177,16 +177,19 @@ struct HaloFaces {
 };
 // (32-bit word indices from the uniform base: F holds K * 48 h^2 / 32 words,
 // below 2^31 for every supported size)
-__device__ __forceinline__ HaloFaces halo_faces(const Geom &g, uint32_t k, int s, const uint32_t *nb) {
+template <int H>
+__device__ __forceinline__ HaloFaces halo_faces(uint32_t k, int s, const uint32_t *nb) {
     HaloFaces hf;
-    const uint32_t fw = g.h2 / 32;  // words per face
+    constexpr uint32_t fw = H * H / 32, fwpo = 6 * fw;  // words per face, per octant
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int bit = (s >> a) & 1;
         const uint32_t c = (uint32_t)(s ^ (1 << a));
         const uint32_t kmi = bit ? k : nb[2 * a], kpi = bit ? nb[2 * a + 1] : k;  // below / above
-        hf.lo[a] = (kmi * 8u + c) * g.fwpo + (uint32_t)(2 * a + 1) * fw;
-        hf.hi[a] = (kpi * 8u + c) * g.fwpo + (uint32_t)(2 * a) * fw;
+        // domain indices stay below 2^22 (fewer than 2^34 sites, at least 4096 per
+        // domain): a 24-bit multiply
+        hf.lo[a] = __umul24(kmi, 8u * fwpo) + c * fwpo + (uint32_t)(2 * a + 1) * fw;
+        hf.hi[a] = __umul24(kpi, 8u * fwpo) + c * fwpo + (uint32_t)(2 * a) * fw;
     }
     return hf;
 }
@@ -303,7 +306,7 @@ __device__ __forceinline__ void load16_words(const Geom &g, uint32_t k, int s, b
 // the halo words of the axes in the mask `axes` (bit a: axis a)
 __device__ __forceinline__ void load16_faces(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
                                              int axes, Raw<16> &r) {
-    const HaloFaces hf = halo_faces(g, k, s, nb);
+    const HaloFaces hf = halo_faces<16>(k, s, nb);
     const Views vw = views_of(g);
     // x faces: bit ly + 16 lz -> half-word l; y faces: bit lx + 16 lz -> half-word l
     if (axes & 1) {
@@ -363,7 +366,7 @@ __device__ __forceinline__ void load8_words(const Geom &g, uint32_t k, int s, bo
 __device__ __forceinline__ void load8_faces(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
                                             int axes, Raw<8> &r) {
     const int lz = l >> 1, p = l & 1;
-    const HaloFaces hf = halo_faces(g, k, s, nb);
+    const HaloFaces hf = halo_faces<8>(k, s, nb);
     const Views vw = views_of(g);
     // x faces: bit ly + 8 lz; rows 4p..4p+3 of plane lz = bits 4l .. 4l + 3
     if (axes & 1) {
