@@ -12,6 +12,7 @@
 //   k_finalize one thread: clock (step 5), counters, observation record.
 // These kernels are generic over the spin layout and serve as the reference
 // launch shape for the persistent engine.
+#include "api_internal.hpp"
 #include "spkmc_device.hpp"
 
 namespace spkmc {
@@ -334,6 +335,13 @@ hipError_t launch_observables(const Geom &g, hipStream_t stream) {
 }
 
 hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream_t stream) {
+    if (rows_supported(g)) {
+        // PACKED lattices with octant edge 8 or 16: the row kernels, then step 5 here
+        hipError_t e = launch_cycle_rows(g, n, stream);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, stream, g, n, obs_every);
+        return hipGetLastError();
+    }
     unsigned bin_block = g.h3 >= 256 ? 256 : 64;
     const unsigned lines = g.K * g.lpd;
     unsigned sel_blocks = (lines + 3) / 4;

@@ -557,6 +557,84 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
     return v;
 }
 
+// --- pieces of a cycle shared by the persistent kernels and the two-launch
+// (per-cycle) row kernels
+
+// One row's class for a target: lane c of the row tests class c against the
+// line's running sums acc (-1: the null event).
+__device__ __forceinline__ int row_class(const double *acc, bool valid, double target, int l, int row) {
+    const bool hit = valid && l < 14 && target < acc[l < 14 ? l : 13];
+    const uint64_t bal = __ballot(hit);
+    const uint32_t rowbits = (uint32_t)(bal >> (16 * (row & 3))) & 0xFFFFu;
+    return rowbits ? __builtin_ctz(rowbits) : -1;
+}
+
+// The event of a row for class cs with ncs sites: the j-th site of the class in
+// canonical order (j from the uniform uz), written into the row's selection slot
+// as (cs << 12) | q, or kNoEvent.  Every lane of the row takes part.
+template <int H>
+__device__ __forceinline__ void select_site(const Planes<H> &pl, int cs, uint32_t ncs, uint32_t uz, int l,
+                                            uint32_t *slot, DevState *st) {
+    constexpr int WPL = Planes<H>::W;
+    if (l == 0) *slot = kNoEvent;
+    const uint32_t j = cs >= 0 ? mul_index(uz, ncs) : 0u;
+    // class cs as (spin, n_up pattern): up spin (cs >= 7): n_up = cs - 7; down
+    // spin: n_up = 6 - cs.  A row without an event never uses its masks.
+    const int up = cs >= 7, v = up ? cs - 7 : 6 - cs;
+    const uint32_t ps = up ? 0xFFFFFFFFu : 0u;  // the pattern each plane must equal
+    const uint32_t p0 = (v & 1) ? 0xFFFFFFFFu : 0u, p1 = (v & 2) ? 0xFFFFFFFFu : 0u;
+    const uint32_t p2 = (v & 4) ? 0xFFFFFFFFu : 0u;
+    uint32_t mk[WPL], cum[WPL];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int p = 0; p < WPL; ++p) {
+        // sites of class cs: no plane differs from its pattern; (a ^ b) | c per step
+        uint32_t d = pl.S[p] ^ ps;
+        d = bop<kXorOr>(pl.b0[p], p0, d);
+        d = bop<kXorOr>(pl.b1[p], p1, d);
+        mk[p] = bop<kXorNor>(pl.b2[p], p2, d);
+        cnt = bcnt_acc(mk[p], cnt);
+        cum[p] = cnt;  // running count over the lane's words
+    }
+    // inclusive prefix over the 16 lanes of the row (canonical order = lane order)
+    const uint32_t incl = row_scan(cnt);
+    const uint32_t excl = incl - cnt;
+    if (cs >= 0 && l == 15 && j >= incl) atomicOr(&st->error, kErrSelect);  // counts disagree with masks
+    if (cs >= 0 && j >= excl && j < incl) {
+        // the word holding the target: as many words as have running counts not
+        // above its rank; then its rank inside that word
+        const uint32_t r0 = j - excl;
+        uint32_t wsel = 0;
+#pragma unroll
+        for (int p = 0; p + 1 < WPL; ++p) wsel += cum[p] <= r0 ? 1u : 0u;
+        uint32_t before = 0, msk = mk[0];
+#pragma unroll
+        for (int p = 1; p < WPL; ++p)
+            if (wsel == (uint32_t)p) {
+                before = cum[p - 1];
+                msk = mk[p];
+            }
+        const uint32_t q = (uint32_t)(l * WPL) * 32 + wsel * 32 + (uint32_t)nth_set_bit(msk, r0 - before);
+        *slot = ((uint32_t)cs << 12) | q;  // after lane 0's store, same wavefront
+    }
+}
+
+// Flip site q of octant (k, so): its spin word and the face copies it appears in.
+template <int H>
+__device__ __forceinline__ void flip_site(const Geom &g, uint32_t k, int so, uint32_t q) {
+    constexpr uint32_t wpo = H * H * H / 32, fwpo = 6 * H * H / 32;
+    flip_word(g.A + ((uint64_t)k * 8 + (uint32_t)so) * wpo + (q >> 5), 1u << (q & 31));
+    const uint32_t lx = q % H, ly = (q / H) % H, lz = q / (H * H);
+    uint32_t *F = g.F + ((uint64_t)k * 8 + (uint32_t)so) * fwpo;
+    constexpr uint32_t e = H - 1, h2 = H * H;
+    if (lx == 0) { uint32_t b = ly + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
+    if (lx == e) { uint32_t b = h2 + ly + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
+    if (ly == 0) { uint32_t b = 2 * h2 + lx + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
+    if (ly == e) { uint32_t b = 3 * h2 + lx + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
+    if (lz == 0) { uint32_t b = 4 * h2 + lx + H * ly; flip_word(F + (b >> 5), 1u << (b & 31)); }
+    if (lz == e) { uint32_t b = 5 * h2 + lx + H * ly; flip_word(F + (b >> 5), 1u << (b & 31)); }
+}
+
 // wall clock (100 MHz) for bounded waits
 __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
@@ -930,62 +1008,10 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             const uint32_t kd = kbase + (uint32_t)((l < P ? l : 0) * rows + row);
             dw = philox10((uint32_t)n, (uint32_t)(n >> 32), line_dom(kd), (uint32_t)line_oct(kd, s), g.seed);
         }
-        constexpr int WPL = Planes<H>::W;
-        // one row's class for a target: lane c of the row tests class c (-1: null)
-        auto row_class = [&](uint32_t ld, bool valid, double target) -> int {
-            const bool hit = valid && l < 14 && target < sh.acc[ld][l < 14 ? l : 13];
-            const uint64_t bal = __ballot(hit);
-            const uint32_t rowbits = (uint32_t)(bal >> (16 * (row & 3))) & 0xFFFFu;
-            return rowbits ? __builtin_ctz(rowbits) : -1;
+        // sites of class c on line ld
+        auto line_count = [&](uint32_t ld, int c) -> uint32_t {
+            return INC ? hcount(sh.histp[ld][s], c) : sh.hist[ld][c];
         };
-        // the event of pass pp's row for class cs: the j-th site of the class in
-        // canonical order, into the row's selection slot
-        auto select_site = [&](int pp, uint32_t ld, int cs, uint32_t uz) {
-            if (l == 0) sh.selq[ld] = kNoEvent;
-            uint32_t ncs = 0;
-            if (cs >= 0) ncs = INC ? hcount(sh.histp[ld][s], cs) : sh.hist[ld][cs];
-            const uint32_t j = cs >= 0 ? mul_index(uz, ncs) : 0u;
-            // class cs as (spin, n_up pattern): up spin (cs >= 7): n_up = cs - 7; down
-            // spin: n_up = 6 - cs.  A row without an event never uses its masks.
-            const int up = cs >= 7, v = up ? cs - 7 : 6 - cs;
-            const uint32_t ps = up ? 0xFFFFFFFFu : 0u;  // the pattern each plane must equal
-            const uint32_t p0 = (v & 1) ? 0xFFFFFFFFu : 0u, p1 = (v & 2) ? 0xFFFFFFFFu : 0u;
-            const uint32_t p2 = (v & 4) ? 0xFFFFFFFFu : 0u;
-            uint32_t mk[WPL], cum[WPL];
-            uint32_t cnt = 0;
-#pragma unroll
-            for (int p = 0; p < WPL; ++p) {
-                // sites of class cs: no plane differs from its pattern; (a ^ b) | c per step
-                uint32_t d = pl[pp].S[p] ^ ps;
-                d = bop<kXorOr>(pl[pp].b0[p], p0, d);
-                d = bop<kXorOr>(pl[pp].b1[p], p1, d);
-                mk[p] = bop<kXorNor>(pl[pp].b2[p], p2, d);
-                cnt = bcnt_acc(mk[p], cnt);
-                cum[p] = cnt;  // running count over the lane's words
-            }
-            // inclusive prefix over the 16 lanes of the row (canonical order = lane order)
-            const uint32_t incl = row_scan(cnt);
-            const uint32_t excl = incl - cnt;
-            if (cs >= 0 && l == 15 && j >= incl) atomicOr(&st->error, kErrSelect);  // counts disagree with masks
-            if (cs >= 0 && j >= excl && j < incl) {
-                // the word holding the target: as many words as have running counts not
-                // above its rank; then its rank inside that word
-                const uint32_t r0 = j - excl;
-                uint32_t wsel = 0;
-#pragma unroll
-                for (int p = 0; p + 1 < WPL; ++p) wsel += cum[p] <= r0 ? 1u : 0u;
-                uint32_t before = 0, msk = mk[0];
-#pragma unroll
-                for (int p = 1; p < WPL; ++p)
-                    if (wsel == (uint32_t)p) {
-                        before = cum[p - 1];
-                        msk = mk[p];
-                    }
-                const uint32_t q = (uint32_t)(l * WPL) * 32 + wsel * 32 + (uint32_t)nth_set_bit(msk, r0 - before);
-                sh.selq[ld] = ((uint32_t)cs << 12) | q;  // after lane 0's store, same wavefront
-            }
-        };
-
         uint32_t cpred = 0;  // per pass: predicted class + 1, five bits each
         {
             const double Rspec = bound ? g.rbound : sh.rpred[s];
@@ -993,9 +1019,9 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             for (int pp = 0; pp < P; ++pp) {
                 const uint32_t ld = (uint32_t)(pp * rows + row);
                 const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
-                const int cs = row_class(ld, ld < nvalid, unit53(ux, uy) * Rspec);
+                const int cs = row_class(sh.acc[ld], ld < nvalid, unit53(ux, uy) * Rspec, l, row);
                 cpred |= (uint32_t)(cs + 1) << (5 * pp);
-                select_site(pp, ld, cs, uz);
+                select_site<H>(pl[pp], cs, cs >= 0 ? line_count(ld, cs) : 0u, uz, l, &sh.selq[ld], st);
             }
         }
 
@@ -1050,8 +1076,9 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             for (int pp = 0; pp < P; ++pp) {
                 const uint32_t ld = (uint32_t)(pp * rows + row);
                 const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
-                const int cs = row_class(ld, ld < nvalid, unit53(ux, uy) * Rmax);
-                if ((uint32_t)(cs + 1) != ((cpred >> (5 * pp)) & 31u)) select_site(pp, ld, cs, uz);
+                const int cs = row_class(sh.acc[ld], ld < nvalid, unit53(ux, uy) * Rmax, l, row);
+                if ((uint32_t)(cs + 1) != ((cpred >> (5 * pp)) & 31u))
+                    select_site<H>(pl[pp], cs, cs >= 0 ? line_count(ld, cs) : 0u, uz, l, &sh.selq[ld], st);
             }
         }
         __syncthreads();
@@ -1118,16 +1145,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                 if (ax != 0) continue;
                 hmove(sh.histp[ld][so], cs, site_class(!up, up ? cs - 7 : 6 - cs));
             }
-            flip_word(g.A + ((uint64_t)k * 8 + so) * g.wpo + (q >> 5), 1u << (q & 31));
-            const uint32_t lx = q % H, ly = (q / H) % H, lz = q / (H * H);
-            uint32_t *F = g.F + ((uint64_t)k * 8 + so) * g.fwpo;
-            constexpr uint32_t e = H - 1, h2 = H * H;
-            if (lx == 0) { uint32_t b = ly + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
-            if (lx == e) { uint32_t b = h2 + ly + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
-            if (ly == 0) { uint32_t b = 2 * h2 + lx + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
-            if (ly == e) { uint32_t b = 3 * h2 + lx + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
-            if (lz == 0) { uint32_t b = 4 * h2 + lx + H * ly; flip_word(F + (b >> 5), 1u << (b & 31)); }
-            if (lz == e) { uint32_t b = 5 * h2 + lx + H * ly; flip_word(F + (b >> 5), 1u << (b & 31)); }
+            flip_site<H>(g, k, so, q);
             myF += 1;
             mydM += cs >= 7 ? -2 : 2;              // the class carries the old spin
             mydB += 12 - 4 * (long long)(cs % 7);  // and its aligned count
@@ -1287,6 +1305,190 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(Replica R) {
     persistent_body<H, P, BLOCK, INC, LPD>(R, blockIdx.x, sh);
 }
 
+// ---------------------------------------------------------------------------
+// The per-cycle engine's row kernels (PACKED, octant edge 8 or 16): one cycle in
+// two launches, for lattices of any size.  k_rows_bin bins every line with the
+// persistent kernel's rows and passes (step 1) and takes the maximum (step 2)
+// into st->rmax[0]; k_rows_select derives the class planes again, draws,
+// selects and flips (steps 3, 4, 4b; step 6 is the launch boundary); the
+// per-cycle k_finalize keeps the clock, the counters and the records (step 5).
+struct RowsShared {
+    uint32_t zbuf[64][24];             // per row: z face words below (8), above (8), zeros (8)
+    uint32_t nbdom[kMaxWgDomains][6];  // per line: its domain's six neighbour domains
+    double acc[kMaxWgDomains][14];     // per line: running FP64 sums of the frequency line
+    uint32_t hist[kMaxWgDomains][14];  // per line: class counts
+    uint32_t selq[kMaxWgDomains];      // per line: (class << 12) | site q, or kNoEvent
+    unsigned long long wmax;           // the workgroup's largest line (FP64 bits)
+    long long red[3][16];
+};
+
+template <int H, int BLOCK, int LPD>
+struct RowsGeometry {
+    static constexpr int rows = BLOCK / 16, P = 4;
+    static constexpr uint32_t D = rows * P;  // lines of one workgroup
+    const Geom &g;
+    uint32_t lpd, kbase, nvalid;
+    __device__ RowsGeometry(const Geom &g_) : g(g_) {
+        lpd = LPD ? (uint32_t)LPD : g.lpd;
+        const uint32_t NL = g.K * lpd;
+        kbase = blockIdx.x * D;
+        nvalid = kbase >= NL ? 0u : (NL - kbase < D ? NL - kbase : D);
+    }
+    __device__ uint32_t dom(uint32_t line) const { return lpd == 1 ? line : line >> 2; }
+    __device__ int oct(uint32_t line, int colour) const {
+        return lpd == 1 ? colour : two_colour_octant(colour, line & 3u);
+    }
+    // the neighbour domains of every line of the workgroup, into LDS
+    __device__ void neighbours(uint32_t (*nbdom)[6]) const {
+        for (uint32_t i = threadIdx.x; i < nvalid * 6; i += BLOCK) {
+            const uint32_t ldm = i / 6;
+            const int dir = (int)(i % 6), a = dir >> 1;
+            const DomainCoord c = dcoord(dom(kbase + ldm), g.nd);
+            int kc[3] = {c.kx, c.ky, c.kz};
+            kc[a] = (dir & 1) ? wrapp(kc[a], g.nd) : wrapm(kc[a], g.nd);
+            nbdom[ldm][dir] = dindex(kc[0], kc[1], kc[2], g.nd);
+        }
+    }
+};
+
+template <int H, int BLOCK, int LPD>
+__global__ void __launch_bounds__(BLOCK) k_rows_bin(Geom g, uint64_t n) {
+    __shared__ RowsShared sh;
+    using RG = RowsGeometry<H, BLOCK, LPD>;
+    constexpr int rows = RG::rows, P = RG::P;
+    const RG rg(g);
+    const int tid = threadIdx.x, row = tid >> 4, l = tid & 15;
+    const int s = cycle_draw(g.seed, n, rg.lpd == 4).colour;
+    rg.neighbours(sh.nbdom);
+    if (tid == 0) sh.wmax = 0;
+    if (l < 8) sh.zbuf[row][16 + l] = 0;
+    __syncthreads();
+    Raw<H> raw[P];
+#pragma unroll
+    for (int pp = 0; pp < P; ++pp) {
+        const uint32_t ld = (uint32_t)(pp * rows + row);
+        const bool valid = ld < rg.nvalid;
+        load_octant<H>(g, rg.dom(rg.kbase + ld), rg.oct(rg.kbase + ld, s), valid, l, sh.nbdom[valid ? ld : 0],
+                       raw[pp]);
+    }
+#pragma unroll
+    for (int pp = 0; pp < P; ++pp) {
+        const uint32_t ld = (uint32_t)(pp * rows + row);
+        const bool valid = ld < rg.nvalid;
+        Planes<H> pl;
+        uint32_t m[13];
+#pragma unroll
+        for (int i = 0; i < 13; ++i) m[i] = 0;
+        compute_octant<H, true>(raw[pp], valid, l, sh.zbuf[row], pl, m);
+        uint32_t mp[7];  // row totals, two to a word
+#pragma unroll
+        for (int i = 0; i < 6; ++i) mp[i] = row_scan(m[2 * i] | (m[2 * i + 1] << 16));
+        mp[6] = row_scan(m[12]);
+        if (l == 15 && valid) {
+            uint32_t mm[13], hc[14];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                mm[2 * i] = mp[i] & 0xFFFFu;
+                mm[2 * i + 1] = mp[i] >> 16;
+            }
+            mm[12] = mp[6];
+            hist_from_moments(mm, (uint32_t)(H * H * H), hc);
+            const uint64_t f = rg.kbase + ld;
+            for (int c = 0; c < 16; ++c) g.hist[f * 16 + c] = c < 14 ? hc[c] : 0u;
+            const double Rk = line_total(hc, g.r);
+            g.Rk[f] = Rk;
+            atomicMax(&sh.wmax, (unsigned long long)double_to_bits(Rk));
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && rg.nvalid && !(g.variant & SPKMC_VARIANT_RMAX_BOUND))
+        atomicMax((unsigned long long *)&g.st->rmax[0], sh.wmax);
+}
+
+template <int H, int BLOCK, int LPD>
+__global__ void __launch_bounds__(BLOCK) k_rows_select(Geom g, uint64_t n) {
+    __shared__ RowsShared sh;
+    using RG = RowsGeometry<H, BLOCK, LPD>;
+    constexpr int rows = RG::rows, P = RG::P;
+    constexpr uint32_t D = RG::D;
+    const RG rg(g);
+    const int tid = threadIdx.x, row = tid >> 4, l = tid & 15;
+    const int s = cycle_draw(g.seed, n, rg.lpd == 4).colour;
+    const double Rmax = (g.variant & SPKMC_VARIANT_RMAX_BOUND) ? g.rbound : bits_to_double(g.st->rmax[0]);
+    rg.neighbours(sh.nbdom);
+    if (l < 8) sh.zbuf[row][16 + l] = 0;
+    // the counts of every line and their running sums, in the order of step 1
+    for (uint32_t i = tid; i < D; i += BLOCK) {
+        double a = 0.0;
+        for (int c = 0; c < 14; ++c) {
+            const uint32_t cnt = i < rg.nvalid ? g.hist[(uint64_t)(rg.kbase + i) * 16 + c] : 0u;
+            sh.hist[i][c] = cnt;
+            double term = (double)cnt * g.r[c];
+            a = a + term;
+            sh.acc[i][c] = a;
+        }
+    }
+    __syncthreads();
+    Raw<H> raw[P];
+#pragma unroll
+    for (int pp = 0; pp < P; ++pp) {
+        const uint32_t ld = (uint32_t)(pp * rows + row);
+        const bool valid = ld < rg.nvalid;
+        load_octant<H>(g, rg.dom(rg.kbase + ld), rg.oct(rg.kbase + ld, s), valid, l, sh.nbdom[valid ? ld : 0],
+                       raw[pp]);
+    }
+    // lane pp of each row draws for the row's line of pass pp
+    U4 dw;
+    {
+        const uint32_t kd = rg.kbase + (uint32_t)((l < P ? l : 0) * rows + row);
+        dw = philox10((uint32_t)n, (uint32_t)(n >> 32), rg.dom(kd), (uint32_t)rg.oct(kd, s), g.seed);
+    }
+#pragma unroll
+    for (int pp = 0; pp < P; ++pp) {
+        const uint32_t ld = (uint32_t)(pp * rows + row);
+        const bool valid = ld < rg.nvalid;
+        Planes<H> pl;
+        uint32_t m[13];
+        compute_octant<H, false>(raw[pp], valid, l, sh.zbuf[row], pl, m);
+        const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
+        const int cs = row_class(sh.acc[ld], valid, unit53(ux, uy) * Rmax, l, row);
+        select_site<H>(pl, cs, cs >= 0 ? sh.hist[ld][cs] : 0u, uz, l, &sh.selq[ld], g.st);
+    }
+    __syncthreads();
+    long long F = 0, dM = 0, dB = 0;
+    for (uint32_t t = tid; t < D; t += BLOCK) {
+        const uint32_t f = sh.selq[t];
+        if (t >= rg.nvalid || f == kNoEvent) continue;
+        const uint32_t cs = f >> 12, q = f & 0xFFFu;
+        flip_site<H>(g, rg.dom(rg.kbase + t), rg.oct(rg.kbase + t, s), q);
+        F += 1;
+        dM += cs >= 7 ? -2 : 2;              // the class carries the old spin
+        dB += 12 - 4 * (long long)(cs % 7);  // and its aligned count
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        F += __shfl_xor(F, o);
+        dM += __shfl_xor(dM, o);
+        dB += __shfl_xor(dB, o);
+    }
+    if ((tid & 63) == 0) {
+        sh.red[0][tid >> 6] = F;
+        sh.red[1][tid >> 6] = dM;
+        sh.red[2][tid >> 6] = dB;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        F = dM = dB = 0;
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            F += sh.red[0][w];
+            dM += sh.red[1][w];
+            dB += sh.red[2][w];
+        }
+        if (F) atomicAdd((unsigned long long *)&g.st->acc_fired[0], (unsigned long long)F);
+        if (dM) atomicAdd((unsigned long long *)&g.st->acc_dM[0], (unsigned long long)dM);
+        if (dB) atomicAdd((unsigned long long *)&g.st->acc_dB[0], (unsigned long long)dB);
+    }
+}
+
 // Many independent lattices in one launch: each workgroup finds its lattice by
 // its workgroup index; lattices never wait for one another.
 template <int H, int P, int BLOCK, bool INC>
@@ -1410,6 +1612,38 @@ hipError_t persistent_configure(const Geom &g, const spkmc_params &p, bool inc, 
         }
     }
     return hipErrorCooperativeLaunchTooLarge;
+}
+
+bool rows_supported(const Geom &g) {
+    return g.layout == SPKMC_LAYOUT_PACKED && (g.h == 8 || g.h == 16) && !(g.variant & SPKMC_VARIANT_RMAX_ALL) &&
+           g.N / 8 < (1ull << 31);
+}
+
+hipError_t launch_cycle_rows(const Geom &g, uint64_t n, hipStream_t stream) {
+    if (!rows_supported(g)) return hipErrorInvalidValue;
+    const uint64_t lines = (uint64_t)g.K * g.lpd;
+    if (g.h == 16) {
+        constexpr int block = 512;
+        const uint32_t grid = (uint32_t)((lines + RowsGeometry<16, block, 1>::D - 1) / RowsGeometry<16, block, 1>::D);
+        if (g.lpd == 4) {
+            hipLaunchKernelGGL((k_rows_bin<16, block, 4>), dim3(grid), dim3(block), 0, stream, g, n);
+            hipLaunchKernelGGL((k_rows_select<16, block, 4>), dim3(grid), dim3(block), 0, stream, g, n);
+        } else {
+            hipLaunchKernelGGL((k_rows_bin<16, block, 1>), dim3(grid), dim3(block), 0, stream, g, n);
+            hipLaunchKernelGGL((k_rows_select<16, block, 1>), dim3(grid), dim3(block), 0, stream, g, n);
+        }
+    } else {
+        constexpr int block = 1024;
+        const uint32_t grid = (uint32_t)((lines + RowsGeometry<8, block, 1>::D - 1) / RowsGeometry<8, block, 1>::D);
+        if (g.lpd == 4) {
+            hipLaunchKernelGGL((k_rows_bin<8, block, 4>), dim3(grid), dim3(block), 0, stream, g, n);
+            hipLaunchKernelGGL((k_rows_select<8, block, 4>), dim3(grid), dim3(block), 0, stream, g, n);
+        } else {
+            hipLaunchKernelGGL((k_rows_bin<8, block, 1>), dim3(grid), dim3(block), 0, stream, g, n);
+            hipLaunchKernelGGL((k_rows_select<8, block, 1>), dim3(grid), dim3(block), 0, stream, g, n);
+        }
+    }
+    return hipGetLastError();
 }
 
 uint64_t persistent_scratch_words(uint64_t K) { return kScratchWordsPerWg * (K / 16 + 2) + 16; }
