@@ -132,7 +132,14 @@ def cpu_baseline(w, cycles):
     dt = time.perf_counter() - t0
     st1 = sim.state()
     fired = st1[1] - st0[1]
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": fired / dt, "unit": "spin-flip events/s", "cores": 1, "kind": "oracle",
+            "host": {"cpu": model, "logical_cpus": os.cpu_count()},
             "sample": f"{cycles} cycles of the same L={w['L']} d={w['domain']} lattice from the same seed "
                       f"({fired} events in {dt:.2f} s; initialisation {t_init:.1f} s not timed)",
             "attempts_per_s": (st1[1] + st1[2] - st0[1] - st0[2]) / dt}
