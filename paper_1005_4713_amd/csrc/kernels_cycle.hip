@@ -275,34 +275,7 @@ __global__ void __launch_bounds__(256) k_select(Geom g, uint64_t n) {
 
 // Step 5 and the bookkeeping of cycle n.
 __global__ void k_finalize(Geom g, uint64_t n, uint32_t obs_every) {
-    if (threadIdx.x != 0) return;
-    DevState *st = g.st;
-    const bool two = g.lpd == 4;
-    CycleDraw cd = cycle_draw(g.seed, n, two);
-    double Rmax = (g.variant & SPKMC_VARIANT_RMAX_BOUND) ? g.rbound : bits_to_double(st->rmax[0]);
-    double dt = -log(cd.ut) / ((two ? 2.0 : 8.0) * Rmax);
-    st->t = st->t + dt;
-    uint64_t f = st->acc_fired[0];
-    st->fired += f;
-    st->nulls += (uint64_t)g.K * g.lpd - f;
-    st->M += st->acc_dM[0];
-    st->B += st->acc_dB[0];
-    st->acc_fired[0] = 0;
-    st->acc_dM[0] = 0;
-    st->acc_dB[0] = 0;
-    st->rmax[0] = 0;
-    st->cycle = n + 1;
-    if (obs_every && ((n + 1) % obs_every) == 0 && g.rec_cap) {
-        spkmc_record r;
-        r.cycle = n + 1;
-        r.fired = st->fired;
-        r.nulls = st->nulls;
-        r.t = st->t;
-        r.M = st->M;
-        r.B = st->B;
-        g.rec[st->rec_count % g.rec_cap] = r;
-        st->rec_count += 1;
-    }
+    if (threadIdx.x == 0) finalize_cycle(g, n, obs_every);
 }
 
 // --------------------------------------------------------------------------- host launchers

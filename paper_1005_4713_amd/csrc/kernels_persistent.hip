@@ -1312,6 +1312,8 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(Replica R) {
 // into st->rmax[0]; k_rows_select derives the class planes again, draws,
 // selects and flips (steps 3, 4, 4b; step 6 is the launch boundary); the
 // per-cycle k_finalize keeps the clock, the counters and the records (step 5).
+constexpr int kRowsPasses = 4;  // passes of the row kernels (128 or 256 lines per workgroup)
+
 struct RowsShared {
     uint32_t zbuf[64][24];             // per row: z face words below (8), above (8), zeros (8)
     uint32_t nbdom[kMaxWgDomains][6];  // per line: its domain's six neighbour domains
@@ -1322,9 +1324,9 @@ struct RowsShared {
     long long red[3][16];
 };
 
-template <int H, int BLOCK, int LPD>
+template <int H, int BLOCK, int LPD, int PASSES>
 struct RowsGeometry {
-    static constexpr int rows = BLOCK / 16, P = 4;
+    static constexpr int rows = BLOCK / 16, P = PASSES;
     static constexpr uint32_t D = rows * P;  // lines of one workgroup
     const Geom &g;
     uint32_t lpd, kbase, nvalid;
@@ -1351,10 +1353,10 @@ struct RowsGeometry {
     }
 };
 
-template <int H, int BLOCK, int LPD>
+template <int H, int BLOCK, int LPD, int PASSES>
 __global__ void __launch_bounds__(BLOCK) k_rows_bin(Geom g, uint64_t n) {
     __shared__ RowsShared sh;
-    using RG = RowsGeometry<H, BLOCK, LPD>;
+    using RG = RowsGeometry<H, BLOCK, LPD, PASSES>;
     constexpr int rows = RG::rows, P = RG::P;
     const RG rg(g);
     const int tid = threadIdx.x, row = tid >> 4, l = tid & 15;
@@ -1405,10 +1407,10 @@ __global__ void __launch_bounds__(BLOCK) k_rows_bin(Geom g, uint64_t n) {
         atomicMax((unsigned long long *)&g.st->rmax[0], sh.wmax);
 }
 
-template <int H, int BLOCK, int LPD>
+template <int H, int BLOCK, int LPD, int PASSES>
 __global__ void __launch_bounds__(BLOCK) k_rows_select(Geom g, uint64_t n) {
     __shared__ RowsShared sh;
-    using RG = RowsGeometry<H, BLOCK, LPD>;
+    using RG = RowsGeometry<H, BLOCK, LPD, PASSES>;
     constexpr int rows = RG::rows, P = RG::P;
     constexpr uint32_t D = RG::D;
     const RG rg(g);
@@ -1619,31 +1621,24 @@ bool rows_supported(const Geom &g) {
            g.N / 8 < (1ull << 31);
 }
 
-hipError_t launch_cycle_rows(const Geom &g, uint64_t n, hipStream_t stream) {
-    if (!rows_supported(g)) return hipErrorInvalidValue;
+template <int H, int BLOCK, int P>
+static hipError_t launch_rows(const Geom &g, uint64_t n, hipStream_t stream) {
     const uint64_t lines = (uint64_t)g.K * g.lpd;
-    if (g.h == 16) {
-        constexpr int block = 512;
-        const uint32_t grid = (uint32_t)((lines + RowsGeometry<16, block, 1>::D - 1) / RowsGeometry<16, block, 1>::D);
-        if (g.lpd == 4) {
-            hipLaunchKernelGGL((k_rows_bin<16, block, 4>), dim3(grid), dim3(block), 0, stream, g, n);
-            hipLaunchKernelGGL((k_rows_select<16, block, 4>), dim3(grid), dim3(block), 0, stream, g, n);
-        } else {
-            hipLaunchKernelGGL((k_rows_bin<16, block, 1>), dim3(grid), dim3(block), 0, stream, g, n);
-            hipLaunchKernelGGL((k_rows_select<16, block, 1>), dim3(grid), dim3(block), 0, stream, g, n);
-        }
+    constexpr uint32_t D = RowsGeometry<H, BLOCK, 1, P>::D;
+    const uint32_t grid = (uint32_t)((lines + D - 1) / D);
+    if (g.lpd == 4) {
+        hipLaunchKernelGGL((k_rows_bin<H, BLOCK, 4, P>), dim3(grid), dim3(BLOCK), 0, stream, g, n);
+        hipLaunchKernelGGL((k_rows_select<H, BLOCK, 4, P>), dim3(grid), dim3(BLOCK), 0, stream, g, n);
     } else {
-        constexpr int block = 1024;
-        const uint32_t grid = (uint32_t)((lines + RowsGeometry<8, block, 1>::D - 1) / RowsGeometry<8, block, 1>::D);
-        if (g.lpd == 4) {
-            hipLaunchKernelGGL((k_rows_bin<8, block, 4>), dim3(grid), dim3(block), 0, stream, g, n);
-            hipLaunchKernelGGL((k_rows_select<8, block, 4>), dim3(grid), dim3(block), 0, stream, g, n);
-        } else {
-            hipLaunchKernelGGL((k_rows_bin<8, block, 1>), dim3(grid), dim3(block), 0, stream, g, n);
-            hipLaunchKernelGGL((k_rows_select<8, block, 1>), dim3(grid), dim3(block), 0, stream, g, n);
-        }
+        hipLaunchKernelGGL((k_rows_bin<H, BLOCK, 1, P>), dim3(grid), dim3(BLOCK), 0, stream, g, n);
+        hipLaunchKernelGGL((k_rows_select<H, BLOCK, 1, P>), dim3(grid), dim3(BLOCK), 0, stream, g, n);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_cycle_rows(const Geom &g, uint64_t n, hipStream_t stream) {
+    if (!rows_supported(g)) return hipErrorInvalidValue;
+    return g.h == 16 ? launch_rows<16, 512, kRowsPasses>(g, n, stream) : launch_rows<8, 1024, kRowsPasses>(g, n, stream);
 }
 
 uint64_t persistent_scratch_words(uint64_t K) { return kScratchWordsPerWg * (K / 16 + 2) + 16; }

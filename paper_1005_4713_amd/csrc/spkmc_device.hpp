@@ -27,8 +27,7 @@ struct alignas(256) DevState {
     uint64_t acc_fired[4]; // per-cycle partial sums of the select phase
     int64_t acc_dM[4];
     int64_t acc_dB[4];
-    uint64_t barrier;      // device-wide barrier arrivals (persistent engine)
-    uint64_t pad1[7];
+    uint64_t pad1[8];
 };
 static_assert(sizeof(DevState) == 256, "DevState must stay 256 bytes");
 
@@ -142,6 +141,39 @@ __device__ inline int line_select(const uint32_t *cnt, const double *r, double t
 
 __device__ inline double bits_to_double(uint64_t b) { return __longlong_as_double((long long)b); }
 __device__ inline uint64_t double_to_bits(double v) { return (uint64_t)__double_as_longlong(v); }
+
+// Step 5 and the bookkeeping of cycle n on the per-cycle engine (one thread,
+// after every workgroup's selection and flips): the clock, the counters from
+// the partials, the observation record; the per-cycle accumulators reset.
+__device__ inline void finalize_cycle(const Geom &g, uint64_t n, uint32_t obs_every) {
+    DevState *st = g.st;
+    const bool two = g.lpd == 4;
+    const CycleDraw cd = cycle_draw(g.seed, n, two);
+    const double Rmax = (g.variant & SPKMC_VARIANT_RMAX_BOUND) ? g.rbound : bits_to_double(st->rmax[0]);
+    const double dt = -log(cd.ut) / ((two ? 2.0 : 8.0) * Rmax);
+    st->t = st->t + dt;
+    const uint64_t f = st->acc_fired[0];
+    st->fired += f;
+    st->nulls += (uint64_t)g.K * g.lpd - f;
+    st->M += st->acc_dM[0];
+    st->B += st->acc_dB[0];
+    st->acc_fired[0] = 0;
+    st->acc_dM[0] = 0;
+    st->acc_dB[0] = 0;
+    st->rmax[0] = 0;
+    st->cycle = n + 1;
+    if (obs_every && ((n + 1) % obs_every) == 0 && g.rec_cap) {
+        spkmc_record r;
+        r.cycle = n + 1;
+        r.fired = st->fired;
+        r.nulls = st->nulls;
+        r.t = st->t;
+        r.M = st->M;
+        r.B = st->B;
+        g.rec[st->rec_count % g.rec_cap] = r;
+        st->rec_count += 1;
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Site addressing.
