@@ -70,3 +70,25 @@ def test_rows_equal_persistent(spkmc, variant, L, d):
     assert a.state() == b.state()
     assert a.records() == b.records()
     assert np.array_equal(a.spins(), b.spins())
+
+
+def test_headline_size_engines_agree(spkmc):
+    """L = 1024, d = 32, T_c, seed 42 (the benchmark's lattice), 200 cycles with a
+    record every 10: the persistent kernel and the row kernels agree bit for bit,
+    and the incremental M and B equal M and B recomputed from the final spins."""
+    from paper_1005_4713_amd import workloads
+    w = workloads.HEADLINE_L1024
+    print("case headline engines 200 cycles", flush=True)
+    runs = []
+    for engine in ("persistent", "cycle"):
+        sim = spkmc.Sim(w["L"], w["domain"], layout="packed", engine=engine, T=w["T"], seed=w["seed"],
+                        record_cap=32)
+        sim.run(200, obs_every=10)
+        runs.append((sim.state(), sim.records(), sim))
+    (sa, ra, a), (sb, rb, b) = runs
+    assert sa == sb and ra == rb
+    s = a.spins().reshape(w["L"], w["L"], w["L"])  # int8, one byte per site
+    assert np.array_equal(s, b.spins().reshape(w["L"], w["L"], w["L"]))
+    M = int(s.sum(dtype=np.int64))
+    B = sum(int((s * np.roll(s, 1, ax)).sum(dtype=np.int64)) for ax in range(3))
+    assert (sa[4], sa[5]) == (M, B)
