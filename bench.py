@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500, help="timed cycles")
     ap.add_argument("--warmup", type=int, default=50, help="untimed cycles before the timed region")
-    ap.add_argument("--workload", default="headline", choices=["headline", "l512", "l128", "batch", "serve", "zeff"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "l512", "l512_sweep", "l128", "batch", "serve", "zeff"])
     ap.add_argument("--variant", default="", help="method variant bits by name, e.g. rmax_bound or two_colours|rmax_all")
     ap.add_argument("--zeff-L", type=int, default=512, help="zeff: lattice edge")
     ap.add_argument("--zeff-tmax", type=float, default=400.0, help="zeff: simulated time to reach")
@@ -323,6 +323,45 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_l512_sweep(args):
+    """The L = 512, d = 16 sweep: three temperatures around T_c, both rate
+    families, both starts, 2000 cycles each with a record every 10.  Per
+    configuration: throughput, UR, and from the records of cycles 1001-2000 the
+    moments of m = M/N: <|m|>, Q = <m^4>/<m^2>^2 and 1 - Q/3 (the ratio the paper
+    prints for U4 and the cumulant it says goes to 0 at low T)."""
+    import numpy as np
+    import torch
+    from paper_1005_4713_amd import spkmc, workloads
+    rows = []
+    for w in workloads.LARGE_L512:
+        print(f"bench: {w['name']}", file=sys.stderr, flush=True)
+        sim = spkmc.Sim(w["L"], w["domain"], J=w["J"], H=w["H"], T=w["T"], seed=w["seed"], rates=w["rates"],
+                        init=w["init"], layout=w["layout"], record_cap=w["cycles"] // w["obs_every"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run(w["cycles"], obs_every=w["obs_every"])
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        st = sim.state()
+        recs = [r for r in sim.records() if r[0] > w["cycles"] // 2]
+        m = np.array([r[4] for r in recs], dtype=np.float64) / float(w["L"]) ** 3
+        m2, m4 = float(np.mean(m ** 2)), float(np.mean(m ** 4))
+        q = m4 / (m2 * m2) if m2 > 0 else float("nan")
+        rows.append({"name": w["name"], "T": w["T"], "rates": w["rates"], "init": w["init"],
+                     "engine": ["auto", "cycle", "persistent", "incremental"][sim.info()["engine"]],
+                     "flips_per_s": st[1] / secs, "us_per_cycle": secs / w["cycles"] * 1e6,
+                     "ur": st[1] / max(st[1] + st[2], 1), "t_end": st[3], "abs_m": float(np.mean(np.abs(m))),
+                     "Q": q, "one_minus_Q_over_3": 1.0 - q / 3.0, "records_used": len(recs)})
+        del sim
+    total_flips = sum(r["flips_per_s"] * r["us_per_cycle"] * 1e-6 * 2000 for r in rows)
+    total_secs = sum(r["us_per_cycle"] * 1e-6 * 2000 for r in rows)
+    print(json.dumps({"metric": "L=512 d=16 sweep: spin-flip events/s over 12 runs of 2000 cycles; Q per run",
+                      "value": total_flips / total_secs, "unit": "spin-flip events/s", "n_gpus": 1,
+                      "higher_is_better": True, "data": "synthetic", "dtype": "u32+f64",
+                      "config": {"workload": "L512_d16_sweep", "runs": len(rows), "cycles": 2000, "obs_every": 10},
+                      "runs": rows}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -346,6 +385,10 @@ def main():
     if args.workload == "zeff":
         torch.cuda.set_device(0)
         bench_zeff(args)
+        return
+    if args.workload == "l512_sweep":
+        torch.cuda.set_device(0)
+        bench_l512_sweep(args)
         return
     w = workload(args.workload)
     torch.cuda.set_device(0)

@@ -113,12 +113,22 @@ def test_single_cycle_launches(spkmc, engine):
     assert np.array_equal(a.spins(), b.spins())
 
 
-def test_large_l512_first_cycles(spkmc):
-    """L = 512 (2^27 sites), d = 16: the first cycles against the oracle."""
-    print("case L512 d16", flush=True)
-    gpu = spkmc.Sim(512, 16, layout="packed", engine="auto", T=4.5115, seed=3, record_cap=16)
-    orc = _orc(512, 16, T=4.5115, seed=3)
-    for n in (2, 3):
+def _l512_sweep():
+    from paper_1005_4713_amd import workloads
+    return workloads.LARGE_L512
+
+
+@pytest.mark.parametrize("w", _l512_sweep(), ids=lambda w: w["name"])
+def test_large_l512_first_cycles(spkmc, w):
+    """L = 512 (2^27 sites), d = 16, every configuration of the sweep (three
+    temperatures around T_c, both rate families, both starts): the first
+    cycles against the oracle."""
+    print("case", w["name"], flush=True)
+    gpu = spkmc.Sim(w["L"], w["domain"], layout="packed", engine="auto", T=w["T"], rates=w["rates"], init=w["init"],
+                    seed=w["seed"], record_cap=16)
+    orc = _orc(w["L"], w["domain"], T=w["T"], seed=w["seed"], rates=w["rates"], init=w["init"])
+    _same(gpu.state(), orc.state())
+    for n in (1, 2):
         gpu.run(n, obs_every=1)
         ro = orc.run(n, obs_every=1)
         for g_, o_ in zip(gpu.records(n), ro):
