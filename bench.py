@@ -71,24 +71,34 @@ def calibrate_copy(mib):
     print(json.dumps({"calibrate_copy_bytes": n, "copies": 3, "read_bytes_per_copy": n, "write_bytes_per_copy": n}))
 
 
+def source_hash(names):
+    """Hash of kernel sources with their comments and layout removed, so that an
+    edit of comments alone does not retire a profile taken with that code."""
+    import hashlib
+    import re
+    m = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        m.update(" ".join(text.split()).encode())
+    return m.hexdigest()[:16]
+
+
 def measured_traffic(workload_name, kernel, variant, steps):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary of this kernel and workload (each scaled by the reading of a plain
     copy of known size); None if there is none or the kernel source changed
     since the counters were taken."""
     import glob
-    import hashlib
     for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")):
         with open(path) as f:
             rec = json.load(f)
         if (rec.get("workload") != workload_name or rec.get("kernel") != kernel
                 or rec.get("variant", "contract") != variant):
             continue
-        m = hashlib.sha256()
-        for name in rec["source_files"]:
-            with open(os.path.join(ROOT, name), "rb") as f:
-                m.update(f.read())
-        if m.hexdigest()[:16] != rec["source_hash"]:
+        if source_hash(rec["source_files"]) != rec["source_hash"]:
             return None, None
         rec["path"] = os.path.relpath(path, ROOT)
         return rec["hbm_bytes_per_cycle"] * steps, rec
@@ -100,17 +110,12 @@ def measured_valu(workload_name, kernel):
     rocprofv3 SQ_INSTS_VALU / SQ_ACTIVE_INST_VALU summary; None if there is none
     or the kernel source changed since they were taken."""
     import glob
-    import hashlib
     for path in glob.glob(os.path.join(ROOT, "profiles", "*_valu.json")):
         with open(path) as f:
             rec = json.load(f)
         if rec.get("workload") != workload_name or rec.get("kernel") != kernel:
             continue
-        m = hashlib.sha256()
-        for name in rec["source_files"]:
-            with open(os.path.join(ROOT, name), "rb") as f:
-                m.update(f.read())
-        if m.hexdigest()[:16] != rec["source_hash"]:
+        if source_hash(rec["source_files"]) != rec["source_hash"]:
             return None
         return {"busy": rec["valu_busy"], "insts_per_wave_cycle": rec["valu_insts_per_wave_cycle"],
                 "source": os.path.relpath(path, ROOT)}

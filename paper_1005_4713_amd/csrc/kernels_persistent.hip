@@ -1,12 +1,19 @@
-// kernels_persistent.hip -- the persistent ("PERSISTENT") engine of the gfx950
-// spkMC library: one cooperative launch runs many cycles (Sec. 3.1 steps 1-6
-// with the sublattice steps 4a/4b of Sec. 3.2) over a bit-packed lattice.
+// kernels_persistent.hip -- the persistent ("PERSISTENT", "INCREMENTAL") engines
+// of the gfx950 spkMC library: one cooperative launch runs many cycles (Sec. 3.1
+// steps 1-6 with the sublattice steps 4a/4b of Sec. 3.2) over a bit-packed
+// lattice; the batch kernel (many lattices in one launch); and the per-cycle
+// engine's row kernels (one cycle in two launches, for lattices whose lines do
+// not fit the device at once), which share the binning, selection and flip code.
 //
 // Work decomposition
-//   * A 16-lane DPP row owns one domain; a workgroup of B threads owns
-//     D = P * B / 16 consecutive domains (numbered kx + nd (ky + nd kz)) for the
-//     whole launch, processed in P passes whose class planes stay in registers
-//     across the R_max exchange.
+//   * A 16-lane DPP row owns one frequency line (a domain's active octant); a
+//     workgroup of B threads owns D = P * B / 16 consecutive lines (domains
+//     numbered kx + nd (ky + nd kz)) for the whole launch, processed in P passes
+//     whose class planes stay in registers from the bin to the flips.
+//   * Each row selects on a predicted R_max (the last one of the same colour)
+//     while the workgroup maxima travel, re-derives its class once the true
+//     R_max is known and selects again only if the class changed; the event
+//     goes into the row's selection slot in LDS, from which the flips are done.
 //   * h = 16: lane l of the row holds plane lz = l of the octant (8 words, two
 //     16-site x rows each); h = 8: lane l holds word l (four 8-site rows of
 //     plane l / 2).  The z neighbours come from the adjacent lanes through DPP
