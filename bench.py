@@ -370,7 +370,7 @@ def bench_l512_sweep(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus above 1 is not supported",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

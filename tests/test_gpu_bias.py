@@ -14,7 +14,7 @@ Also run: the eight-colour contract on the persistent engine.
 Claim checked (Fig. 4): the time-integrated bias over the window is smaller
 than 3 sigma_b, sigma_b^2 = sigma_p^2 + sigma_s^2 (standard errors of the
 parallel and serial means).  The per-time bias of Fig. 3 and the table of
-Fig. 4 are written to gpurun_out/bias_study.json when that folder exists.
+Fig. 4 are written to bias_study.json in the folder SPKMC_RESULTS_DIR names, if set.
 """
 import json
 import math
@@ -99,8 +99,8 @@ def test_bias_within_serial_deviation(spkmc, serial, variant, engine, d):
                    "relative_bias": (mp - ms) / ms,
                    "bias_t": (par.mean(axis=0) - serial.mean(axis=0)).tolist(),
                    "sigma_s_t": serial.std(axis=0, ddof=1).tolist()})
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("SPKMC_RESULTS_DIR", "")
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "bias_study.json"), "w") as f:
             json.dump({"L": L, "T": TC, "grid": GRID.tolist(), "serial_runs": SERIAL_RUNS,
                        "parallel_runs": PARALLEL_RUNS, "serial_mean_t": serial.mean(axis=0).tolist(),
