@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--replicas", type=int, default=256, help="batch / serve: lattices in the replica mix")
     ap.add_argument("--cycles", type=int, default=1000, help="batch / serve: cycles per lattice")
     ap.add_argument("--macro-cycles", type=int, default=100, help="serve: cycles per macro-step")
-    ap.add_argument("--engine", default="auto", choices=["auto", "cycle", "persistent", "incremental"])
+    ap.add_argument("--engine", default="auto", choices=["auto", "cycle", "persistent", "incremental", "slab"])
     ap.add_argument("--wg-domains", type=int, default=0)
     ap.add_argument("--obs-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -353,7 +353,7 @@ def bench_l512_sweep(args):
         m2, m4 = float(np.mean(m ** 2)), float(np.mean(m ** 4))
         q = m4 / (m2 * m2) if m2 > 0 else float("nan")
         rows.append({"name": w["name"], "T": w["T"], "rates": w["rates"], "init": w["init"],
-                     "engine": ["auto", "cycle", "persistent", "incremental"][sim.info()["engine"]],
+                     "engine": ["auto", "cycle", "persistent", "incremental", "slab"][sim.info()["engine"]],
                      "flips_per_s": st[1] / secs, "us_per_cycle": secs / w["cycles"] * 1e6,
                      "ur": st[1] / max(st[1] + st[2], 1), "t_end": st[3], "abs_m": float(np.mean(np.abs(m))),
                      "Q": q, "one_minus_Q_over_3": 1.0 - q / 3.0, "records_used": len(recs)})
@@ -426,12 +426,15 @@ def main():
     secs = gpu_ms / 1e3
     value = fired / secs
     bytes_cycle = info["bytes_per_cycle"]
-    launches = 1 if info["engine"] in (spkmc.ENGINES["persistent"], spkmc.ENGINES["incremental"]) else 3 * args.steps
+    launches = 1 if info["engine"] in (spkmc.ENGINES["persistent"], spkmc.ENGINES["incremental"],
+                                       spkmc.ENGINES["slab"]) else 3 * args.steps
     achieved = bytes_cycle * args.steps / secs / 1e9
     inc = info["engine"] == spkmc.ENGINES["incremental"]
     lpd = 4 if sim.params.variant & spkmc.VARIANTS["two_colours"] else 1
     kernel = (f"k_persistent<{info['h']}, {info['wg_domains'] * 16 // info['block']}, {info['block']}, "
               f"{str(inc).lower()}, {lpd}>" if launches == 1 else "whole cycle (3 launches)")
+    if info["engine"] == spkmc.ENGINES["slab"]:
+        kernel = "k_slab"
     traffic, traffic_rec = (None, None)
     if launches == 1:
         traffic, traffic_rec = measured_traffic(w["name"], kernel, args.variant or "contract", args.steps)
@@ -450,7 +453,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "L": w["L"], "domain": w["domain"], "T": w["T"], "J": w["J"],
                    "H": w["H"], "rates": w["rates"], "init": w["init"], "seed": w["seed"],
-                   "layout": w["layout"], "engine": ["auto", "cycle", "persistent", "incremental"][info["engine"]],
+                   "layout": w["layout"], "engine": ["auto", "cycle", "persistent", "incremental", "slab"][info["engine"]],
                    "grid": info["grid"], "block": info["block"], "wg_domains": info["wg_domains"],
                    "K": info["K"], "h": info["h"], "obs_every": args.obs_every,
                    "variant": args.variant or "contract"},

@@ -88,8 +88,15 @@ enum { SPKMC_LAYOUT_INT8 = 0, SPKMC_LAYOUT_PACKED = 1 };
  * stay on chip and follow every flip (the flipped site and its six neighbours
  * change class); a cycle classifies its active octant only to locate the
  * selected site, while the R_max exchange is in flight.
+ * SLAB: the persistent launch for octant edge 16 (domain 32), variant 0: the
+ * class counts of every octant, split over its four slabs of four z-planes,
+ * stay in device memory (state_bytes grows by 896 bytes per domain for PACKED
+ * lattices with domain 32) and follow every flip; a cycle reads the counts of
+ * its active octant instead of binning it, and classifies only the slab that
+ * holds the selected site.
  * All engines produce bit-identical trajectories. */
-enum { SPKMC_ENGINE_AUTO = 0, SPKMC_ENGINE_CYCLE = 1, SPKMC_ENGINE_PERSISTENT = 2, SPKMC_ENGINE_INCREMENTAL = 3 };
+enum { SPKMC_ENGINE_AUTO = 0, SPKMC_ENGINE_CYCLE = 1, SPKMC_ENGINE_PERSISTENT = 2, SPKMC_ENGINE_INCREMENTAL = 3,
+       SPKMC_ENGINE_SLAB = 4 };
 
 /* Method variants (bit flags).
  * RMAX_ALL (Sec. 3.1 step 2 read literally): R_max is the maximum over every

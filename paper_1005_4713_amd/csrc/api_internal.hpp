@@ -19,6 +19,10 @@ hipError_t persistent_configure(const Geom &g, const spkmc_params &p, bool inc, 
 hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid,
                              int block, int wg_domains, bool inc, hipStream_t stream);
 uint64_t persistent_scratch_words(uint64_t K);
+// Slab engine (PACKED, octant edge 16, variant 0): support, launch shape, launch.
+bool slab_supported(const Geom &g, const spkmc_params &p, std::string &why);
+hipError_t slab_configure(const Geom &g, int &grid, int &block, int &wg_domains);
+hipError_t launch_slab(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid, hipStream_t stream);
 struct Replica;
 size_t replica_bytes();
 hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t *ncycles, uint32_t obs_every,

@@ -675,7 +675,8 @@ struct PersistShared {
 // Sum the partials of the oldest pending record over all workgroups (one
 // wavefront) and append the record.  The caller guarantees every workgroup has
 // stored them.
-__device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch &xs, PersistShared &sh, uint32_t G,
+template <class SH>
+__device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch &xs, SH &sh, uint32_t G,
                                             int lane, uint64_t n0, uint64_t fired0, uint64_t nulls0, int64_t M0,
                                             int64_t B0) {
     const uint32_t slot = sh.pend_head % kRecBanks;
@@ -709,8 +710,8 @@ __device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch 
 
 // Wait until the neighbour workgroups in direction dir (all six directions for
 // dir < 0) have completed `upto` cycles; false on a timeout (error set).
-template <int BLOCK>
-__device__ __forceinline__ bool wait_neighbours(const PersistScratch &xs, DevState *st, PersistShared &sh, uint32_t G,
+template <int BLOCK, class SH>
+__device__ __forceinline__ bool wait_neighbours(const PersistScratch &xs, DevState *st, SH &sh, uint32_t G,
                                                 int dir, uint64_t upto) {
     const int tid = threadIdx.x;
     for (int d = dir < 0 ? 0 : dir; d < (dir < 0 ? 6 : dir + 1); ++d) {
@@ -1541,6 +1542,596 @@ __global__ void k_persistent_prep_batch(const Replica *__restrict__ reps, uint32
 }
 
 // ---------------------------------------------------------------------------
+// Slab engine (PACKED, octant edge 16, eight colours, R_max exchanged).  The
+// class counts of every octant live in device memory, split over its four
+// slabs of four z-planes (28 words per octant: class c, slabs 2i and 2i + 1 as
+// the 16-bit halves of word 2c + i).  A cycle reads the counts of the active
+// octants instead of binning them (step 1), takes the frequency lines and
+// R_max from them (steps 1 and 2), and locates the selected site (step 4b) by
+// classifying only the slab whose running count of the chosen class passes the
+// site's rank.  Each flip moves the flipped site and its six neighbours between
+// classes (step 6): the counts of the active octant in LDS, written back at the
+// end of the cycle (no other domain's flip reaches an active octant), those of
+// the face-adjacent octants by device atomics.
+// ---------------------------------------------------------------------------
+constexpr int kSlabRows = 32, kSlabPasses = 4, kSlabBlock = kSlabRows * 16;
+constexpr uint32_t kSlabDomains = kSlabRows * kSlabPasses;  // domains of one workgroup
+constexpr uint32_t kSlabWords = 28;                         // slab count words per octant
+// per domain in LDS: the 128 words of the active octant (plane z: words 8z ..
+// 8z + 7, word w holding rows 2w and 2w + 1), then its halo faces x below, x
+// above, y below, y above, z below, z above (8 words each, the face-copy layout)
+constexpr int kOctLds = 176;
+constexpr int kFxm = 128, kFxp = 136, kFym = 144, kFyp = 152, kFzm = 160, kFzp = 168;
+
+struct SlabShared {
+    double r[14];
+    uint32_t oct[kSlabDomains][kOctLds];    // active octants and their halos
+    uint32_t sc[kSlabDomains][kSlabWords];  // slab counts of the active octants
+    uint32_t cnt[kSlabDomains][14];         // class counts of the active octants
+    double acc[kSlabDomains][14];           // running FP64 sums of the frequency lines
+    double rk[kSlabDomains];
+    uint32_t zbuf[kSlabRows][24];           // binning at launch start: z face words per row
+    uint32_t nbdom[kSlabDomains][6];
+    uint32_t selq[kSlabDomains];
+    double rpred[8];
+    double rmax;
+    int abort;
+    uint32_t nbr_bits[6][kMaxGrid / 32];
+    uint32_t nbr_cnt[6];
+    uint32_t nbr[6][kMaxNbr];
+    long long red[3][16];
+    uint32_t pend_head, pend_tail;
+    uint64_t pend_cycle[kRecBanks];
+    double pend_t[kRecBanks];
+    uint32_t pend_bank[kRecBanks];
+};
+
+__device__ __forceinline__ void st32(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spin (1 = up) of the active octant at local (x, y, z), each in [-1, 16] and
+// at most one outside [0, 16): the octant's words or one of its halo faces.
+__device__ __forceinline__ uint32_t slab_spin(const uint32_t *o, int x, int y, int z) {
+    int base = 0, b = x + 16 * y + 256 * z;
+    if ((unsigned)x > 15u) base = x < 0 ? kFxm : kFxp, b = y + 16 * z;
+    if ((unsigned)y > 15u) base = y < 0 ? kFym : kFyp, b = x + 16 * z;
+    if ((unsigned)z > 15u) base = z < 0 ? kFzm : kFzp, b = x + 16 * y;
+    return (o[base + (b >> 5)] >> (b & 31)) & 1u;
+}
+// Class of the site at octant-local (x, y, z) inside the octant, from the words
+// and halo in LDS.
+__device__ __forceinline__ int slab_class_lds(const uint32_t *o, int x, int y, int z) {
+    const uint32_t nup = slab_spin(o, x - 1, y, z) + slab_spin(o, x + 1, y, z) + slab_spin(o, x, y - 1, z) +
+                         slab_spin(o, x, y + 1, z) + slab_spin(o, x, y, z - 1) + slab_spin(o, x, y, z + 1);
+    return site_class(slab_spin(o, x, y, z), (int)nup);
+}
+// Spin at domain-local (x, y, z), each in [-2h, 4h), of the domain at c (the
+// periodic neighbour domain outside [0, 2h)), and the domain, octant and local
+// z of the site.
+__device__ __forceinline__ uint32_t spin_at16(const Geom &g, DomainCoord c, int x, int y, int z, uint32_t &k,
+                                              int &o, int &lz) {
+    const int cx = x < 0 ? wrapm(c.kx, g.nd) : x >= 32 ? wrapp(c.kx, g.nd) : c.kx;
+    const int cy = y < 0 ? wrapm(c.ky, g.nd) : y >= 32 ? wrapp(c.ky, g.nd) : c.ky;
+    const int cz = z < 0 ? wrapm(c.kz, g.nd) : z >= 32 ? wrapp(c.kz, g.nd) : c.kz;
+    x &= 31, y &= 31, z &= 31;
+    o = (x >> 4) | ((y >> 4) << 1) | ((z >> 4) << 2);
+    lz = z & 15;
+    k = dindex(cx, cy, cz, g.nd);
+    const uint32_t q = (uint32_t)((x & 15) + 16 * ((y & 15) + 16 * lz));
+    const uint32_t word = (k * 8u + (uint32_t)o) * 128u + (q >> 5);
+    return (ld32(&g.A[word]) >> (q & 31)) & 1u;
+}
+
+// A site of slab b leaves class c_old for c_new: the slab counts of its octant.
+__device__ __forceinline__ void slab_move_lds(uint32_t *sc, int c_old, int c_new, int b) {
+    const int sh = 16 * (b & 1);
+    atomicAdd(&sc[2 * c_old + (b >> 1)], 0u - (1u << sh));
+    atomicAdd(&sc[2 * c_new + (b >> 1)], 1u << sh);
+}
+__device__ __forceinline__ void slab_move_dev(uint32_t *sc, int c_old, int c_new, int b) {
+    const int sh = 16 * (b & 1);
+    (void)__hip_atomic_fetch_add(&sc[2 * c_old + (b >> 1)], 0u - (1u << sh), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    (void)__hip_atomic_fetch_add(&sc[2 * c_new + (b >> 1)], 1u << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The event of the row of domain ld for class cs (-1: none), written into its
+// selection slot as (cs << 12) | q, or kNoEvent.  The site is the j-th of class
+// cs in canonical order (j from uz): the slab is the one whose running count of
+// the class passes j; lane l of the row classifies words 2 (l & 3) and
+// 2 (l & 3) + 1 of plane 4 slab + l / 4 of that slab, so the lanes run in
+// canonical order.  Every lane of the row takes part.
+__device__ __forceinline__ void slab_select(const SlabShared &sh, uint32_t ld, int cs, uint32_t uz, int l,
+                                            uint32_t *slot, DevState *st) {
+    if (l == 0) *slot = kNoEvent;
+    const int c = cs >= 0 ? cs : 0;
+    const uint32_t v0 = sh.sc[ld][2 * c], v1 = sh.sc[ld][2 * c + 1];
+    const uint32_t e1 = v0 & 0xFFFFu, e2 = e1 + (v0 >> 16), e3 = e2 + (v1 & 0xFFFFu), ncs = e3 + (v1 >> 16);
+    const uint32_t j = cs >= 0 ? mul_index(uz, ncs) : 0u;
+    const uint32_t b = (j >= e1 ? 1u : 0u) + (j >= e2 ? 1u : 0u) + (j >= e3 ? 1u : 0u);
+    const uint32_t rank = j - (b == 0 ? 0u : b == 1 ? e1 : b == 2 ? e2 : e3);
+    const int pz = 4 * (int)b + (l >> 2), wi = 2 * (l & 3);
+    const uint32_t *o = sh.oct[ld];
+    const uint32_t wa = o[8 * pz + wi], wb = o[8 * pz + wi + 1];
+    // y neighbours: row 2 wi - 1 (the previous word, or the face below) and row
+    // 2 wi + 4 (the word after next, or the face above); a face row of plane pz
+    // is half-word pz & 1 of face word pz / 2
+    const int fh = 16 * (pz & 1);
+    const uint32_t prev = wi == 0 ? ((o[kFym + (pz >> 1)] >> fh) & 0xFFFFu) << 16 : o[8 * pz + wi - 1];
+    const uint32_t next = wi == 6 ? (o[kFyp + (pz >> 1)] >> fh) & 0xFFFFu : o[8 * pz + wi + 2];
+    // z neighbours: planes pz -+ 1, or the z faces (the same word layout as a plane)
+    const int zm = pz == 0 ? kFzm + wi : 8 * (pz - 1) + wi, zp = pz == 15 ? kFzp + wi : 8 * (pz + 1) + wi;
+    const uint32_t zma = o[zm], zmb = o[zm + 1], zpa = o[zp], zpb = o[zp + 1];
+    // x neighbours: the x faces hold rows 2 wi .. 2 wi + 3 of plane pz at bits fh + 2 wi ..
+    const uint32_t xm = o[kFxm + (pz >> 1)] >> (fh + 2 * wi), xp = o[kFxp + (pz >> 1)] >> (fh + 2 * wi);
+    const uint32_t Tma = (xm & 1u) | ((xm & 2u) << 15), Tmb = ((xm >> 2) & 1u) | ((xm & 8u) << 13);
+    const uint32_t Tpa = ((xp & 1u) << 15) | ((xp & 2u) << 30), Tpb = ((xp & 4u) << 13) | ((xp & 8u) << 28);
+    // class cs as (spin, n_up pattern), as in select_site
+    const int up = cs >= 7, v = up ? cs - 7 : 6 - cs;
+    const uint32_t ps = up ? 0xFFFFFFFFu : 0u, p0 = (v & 1) ? 0xFFFFFFFFu : 0u;
+    const uint32_t p1 = (v & 2) ? 0xFFFFFFFFu : 0u, p2 = (v & 4) ? 0xFFFFFFFFu : 0u;
+    uint32_t mk[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const uint32_t w = i ? wb : wa;
+        const uint32_t nxm = bop<kSelAC_BnC>(w << 1, i ? Tmb : Tma, 0xFFFEFFFEu);
+        const uint32_t nxp = bop<kSelAC_BnC>(w >> 1, i ? Tpb : Tpa, 0x7FFF7FFFu);
+        const uint32_t nym = i ? align_hi(wb, wa, 16) : align_hi(wa, prev, 16);
+        const uint32_t nyp = i ? align_hi(next, wb, 16) : align_hi(wb, wa, 16);
+        uint32_t o0, o1, o2;
+        count6(nxm, nxp, nym, nyp, i ? zmb : zma, i ? zpb : zpa, o0, o1, o2);
+        uint32_t d = w ^ ps;
+        d = bop<kXorOr>(o0, p0, d);
+        d = bop<kXorOr>(o1, p1, d);
+        mk[i] = bop<kXorNor>(o2, p2, d);
+    }
+    const uint32_t ca = (uint32_t)__builtin_popcount(mk[0]);
+    const uint32_t tot = bcnt_acc(mk[1], ca);
+    const uint32_t incl = row_scan(tot), excl = incl - tot;
+    if (cs >= 0 && l == 15 && rank >= incl) atomicOr(&st->error, kErrSelect);  // counts disagree with the spins
+    if (cs >= 0 && rank >= excl && rank < incl) {
+        const uint32_t r0 = rank - excl;
+        const bool first = r0 < ca;
+        const uint32_t bit = (uint32_t)(first ? nth_set_bit(mk[0], r0) : nth_set_bit(mk[1], r0 - ca));
+        const uint32_t q = (uint32_t)(256 * pz) + 32u * (uint32_t)(wi + (first ? 0 : 1)) + bit;
+        *slot = ((uint32_t)cs << 12) | q;
+    }
+}
+
+// Bin octant o of every domain of the workgroup into its slab counts in device
+// memory: the 13 moments of each plane (lane), summed over the slab's four
+// lanes, give the slab's histogram.
+__device__ __forceinline__ void slab_bin_octant(const Geom &g, uint32_t kbase, uint32_t nvalid, int o,
+                                                SlabShared &sh) {
+    const int tid = threadIdx.x, row = tid >> 4, l = tid & 15;
+#pragma unroll 1
+    for (int pp = 0; pp < kSlabPasses; ++pp) {
+        const uint32_t ld = (uint32_t)(pp * kSlabRows + row);
+        const bool valid = ld < nvalid;
+        Raw<16> raw;
+        Planes<16> pl;
+        load_octant<16>(g, kbase + ld, o, valid, l, sh.nbdom[valid ? ld : 0], raw);
+        uint32_t m[13];
+#pragma unroll
+        for (int i = 0; i < 13; ++i) m[i] = 0;
+        compute16<true>(raw, valid, l, sh.zbuf[row], pl, m);
+#pragma unroll
+        for (int i = 0; i < 13; ++i) {
+            m[i] += dpp0<kRowShr1>(m[i]);
+            m[i] += dpp0<kRowShr2>(m[i]);  // lane 4 b + 3: the sum over slab b
+        }
+        uint32_t hc[14];
+        hist_from_moments(m, 1024u, hc);
+        // lanes 7 and 15 write slabs 0, 1 and 2, 3 of every class
+        uint32_t *dst = g.sc + ((uint64_t)(kbase + ld) * 8 + (uint32_t)o) * kSlabWords + (l >> 3);
+#pragma unroll
+        for (int c = 0; c < 14; ++c) {
+            const uint32_t lo = dpp0<kRowShr4>(hc[c]);  // lane 4 b + 3 -> 4 b + 7
+            if (valid && (l & 7) == 7) st32(dst + 2 * c, lo | (hc[c] << 16));
+        }
+    }
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, SlabShared &sh) {
+    static_assert(BLOCK == kSlabBlock, "one launch shape");
+    const Geom &g = R.g;
+    const PersistScratch &xs = R.xs;
+    const uint64_t n0 = R.n0, ncycles = R.ncycles;
+    const uint32_t obs_every = R.obs_every;
+    constexpr int nthr = BLOCK, rows = kSlabRows, P = kSlabPasses;
+    const int tid = threadIdx.x;
+    const int row = tid >> 4, l = tid & 15;
+    const uint32_t G = R.G;
+    constexpr uint32_t D = kSlabDomains;
+    const uint32_t kbase = gid * D;
+    const uint32_t nvalid = kbase >= g.K ? 0u : (g.K - kbase < D ? g.K - kbase : D);
+    const bool recorder = gid == 0;
+    const uint64_t n_end = n0 + ncycles;
+
+    for (uint32_t i = tid; i < 6 * (kMaxGrid / 32); i += nthr) (&sh.nbr_bits[0][0])[i] = 0;
+    if (tid == 0) {
+        sh.abort = 0;
+        sh.pend_head = sh.pend_tail = 0;
+    }
+    if (tid < 8) sh.rpred[tid] = 0.0;
+    if (tid < 14) sh.r[tid] = g.r[tid];
+    if (l < 8) sh.zbuf[row][16 + l] = 0;
+    for (uint32_t i = tid; i < nvalid * 6; i += nthr) {
+        uint32_t ldm = i / 6;
+        int dir = (int)(i % 6), a = dir >> 1;
+        DomainCoord c = dcoord(kbase + ldm, g.nd);
+        int kc[3] = {c.kx, c.ky, c.kz};
+        kc[a] = (dir & 1) ? wrapp(kc[a], g.nd) : wrapm(kc[a], g.nd);
+        sh.nbdom[ldm][dir] = dindex(kc[0], kc[1], kc[2], g.nd);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < nvalid * 6; i += nthr) {
+        int dir = (int)(i % 6);
+        uint32_t owner = sh.nbdom[i / 6][dir] / D;
+        if (owner != gid) atomicOr(&sh.nbr_bits[dir][owner >> 5], 1u << (owner & 31));
+    }
+    __syncthreads();
+    if (tid < 6) {
+        uint32_t cnt = 0;
+        for (uint32_t w = 0; w < G; ++w)
+            if ((sh.nbr_bits[tid][w >> 5] >> (w & 31)) & 1u) {
+                if (cnt < kMaxNbr) sh.nbr[tid][cnt] = w;
+                ++cnt;
+            }
+        sh.nbr_cnt[tid] = cnt;
+    }
+    __syncthreads();
+
+    // slab counts of all eight octants from the spins at launch start; they are
+    // complete before this workgroup publishes its first R_max, hence before any
+    // workgroup flips
+#pragma unroll 1
+    for (int o = 0; o < 8; ++o) slab_bin_octant(g, kbase, nvalid, o, sh);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    DevState *st = g.st;
+    const uint64_t fired0 = st->fired, nulls0 = st->nulls;
+    const int64_t M0 = st->M, B0 = st->B;
+    double t = st->t;
+    long long myF = 0, mydM = 0, mydB = 0;
+    uint32_t rec_index = 0;
+    int prev_colour = -1;
+    double lnu = -log(cycle_draw(g.seed, n0, false).ut);
+    uint64_t next_rec = obs_every ? (n0 / obs_every + 1) * obs_every : ~0ull;
+    const int endSC = (int)((uint64_t)g.K * 8u * kSlabWords * 4u);
+    const __amdgpu_buffer_rsrc_t SC = __builtin_amdgcn_make_buffer_rsrc((void *)g.sc, (short)0, endSC, 0x00020000);
+
+    for (uint64_t n = n0; n < n_end; ++n) {
+        const int s = cycle_draw(g.seed, n, false).colour;
+        // step 6 of the previous cycle: the flips (and count moves) that octant s can see
+        if (n > n0) {
+            int diff = s ^ prev_colour;
+            if (diff && !(diff & (diff - 1))) {
+                int a = diff == 1 ? 0 : diff == 2 ? 1 : 2;
+                int dir = 2 * a + ((s >> a) & 1);
+                if (!wait_neighbours<BLOCK>(xs, st, sh, G, dir, n)) break;
+            }
+        }
+        prev_colour = s;
+
+        // --- step 1 from the counts: the slab counts of the active octants first
+        // (the frequency lines need only them), then their words and halos (only
+        // the selection needs them: staged into LDS pass by pass just before it)
+        Raw<16> raw[P];
+        {
+            uint32_t scw[P][2];
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                const uint32_t ld = (uint32_t)(pp * rows + row);
+                const bool valid = ld < nvalid;
+                const int off = valid && l < 14
+                                    ? (int)((((kbase + ld) * 8u + (uint32_t)s) * kSlabWords + 2u * (uint32_t)l) * 4u)
+                                    : endSC;
+                const auto v = __builtin_amdgcn_raw_buffer_load_b64(SC, off, 0, kCoherent);
+                scw[pp][0] = v[0];
+                scw[pp][1] = v[1];
+            }
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                const uint32_t ld = (uint32_t)(pp * rows + row);
+                const bool valid = ld < nvalid;
+                load_octant<16>(g, kbase + ld, s, valid, l, sh.nbdom[valid ? ld : 0], raw[pp]);
+            }
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                const uint32_t ld = (uint32_t)(pp * rows + row);
+                if (l < 14) {
+                    sh.sc[ld][2 * l] = scw[pp][0];
+                    sh.sc[ld][2 * l + 1] = scw[pp][1];
+                    sh.cnt[ld][l] = (scw[pp][0] & 0xFFFFu) + (scw[pp][0] >> 16) + (scw[pp][1] & 0xFFFFu) +
+                                    (scw[pp][1] >> 16);
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < D; i += nthr) {
+            double a = 0.0;
+            for (int c = 0; c < 14; ++c) {
+                double term = (double)sh.cnt[i][c] * sh.r[c];
+                a = a + term;
+                sh.acc[i][c] = a;
+            }
+            sh.rk[i] = i < nvalid ? a : 0.0;
+        }
+        __syncthreads();
+
+        // --- step 2: R_max over all active octants (slot banks as in the re-binning engine)
+        uint64_t *bank = xs.slot + (n & 1) * (uint64_t)G;
+        const uint64_t gen = ((n >> 1) & 1) << 63;
+        if (tid < 64) {
+            double v = 0.0;
+            for (uint32_t i = tid; i < D; i += 64) v = fmax(v, sh.rk[i]);
+            v = wave_max_nonneg(v);
+            if (tid == 63) st64(&bank[gid], double_to_bits(v) | gen);
+        }
+        // --- steps 3, 4 and 4b on the predicted R_max while the maxima travel
+        U4 dw;
+        {
+            const uint32_t kd = kbase + (uint32_t)((l < P ? l : 0) * rows + row);
+            dw = philox10((uint32_t)n, (uint32_t)(n >> 32), kd, (uint32_t)s, g.seed);
+        }
+        uint32_t cpred = 0;
+        {
+            const double Rspec = sh.rpred[s];
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                const uint32_t ld = (uint32_t)(pp * rows + row);
+                // this row's octant into LDS (the row's own lanes read it back)
+                uint32_t *o = sh.oct[ld];
+#pragma unroll
+                for (int w = 0; w < 8; ++w) o[8 * l + w] = raw[pp].W[w];
+                if (!(l & 1)) {
+                    o[kFxm + (l >> 1)] = raw[pp].xm;
+                    o[kFxp + (l >> 1)] = raw[pp].xp;
+                    o[kFym + (l >> 1)] = raw[pp].ym;
+                    o[kFyp + (l >> 1)] = raw[pp].yp;
+                }
+                o[kFzm + l] = raw[pp].zw;  // lanes 8 .. 15: the face above
+                const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
+                const int cs = row_class(sh.acc[ld], ld < nvalid, unit53(ux, uy) * Rspec, l, row);
+                cpred |= (uint32_t)(cs + 1) << (5 * pp);
+                slab_select(sh, ld, cs, uz, l, &sh.selq[ld], st);
+            }
+        }
+        if (tid < 64) {
+            if (recorder && sh.pend_head != sh.pend_tail && sh.pend_cycle[sh.pend_head % kRecBanks] + 2 <= n + 1)
+                emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
+            uint64_t start = now_ticks();
+            double best = 0.0;
+            constexpr int kSlotsPerLane = 4;
+            for (uint32_t base = 0; base < G && !sh.abort; base += 64 * kSlotsPerLane) {
+                uint64_t sv[kSlotsPerLane];
+#pragma unroll
+                for (int i = 0; i < kSlotsPerLane; ++i) {
+                    uint32_t w = base + (uint32_t)i * 64 + tid;
+                    sv[i] = w < G ? ld64(&bank[w]) : gen;
+                }
+                for (;;) {
+                    bool all = true;
+#pragma unroll
+                    for (int i = 0; i < kSlotsPerLane; ++i) {
+                        uint32_t w = base + (uint32_t)i * 64 + tid;
+                        if ((sv[i] & (1ull << 63)) != gen) {
+                            all = false;
+                            sv[i] = ld64(&bank[w]);
+                        }
+                    }
+                    if (__all(all)) break;
+                    __builtin_amdgcn_s_sleep(1);
+                    if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
+                        atomicOr(&st->error, kErrBarrierTimeout);
+                        sh.abort = 1;
+                        break;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < kSlotsPerLane; ++i) best = fmax(best, bits_to_double(sv[i] & ~(1ull << 63)));
+            }
+            best = wave_max_nonneg(best);
+            if (tid == 63) sh.rmax = best;
+        }
+        __syncthreads();
+        if (sh.abort) break;
+        const double Rmax = sh.rmax;
+        {
+            if (tid == 0) sh.rpred[s] = Rmax;
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                const uint32_t ld = (uint32_t)(pp * rows + row);
+                const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
+                const int cs = row_class(sh.acc[ld], ld < nvalid, unit53(ux, uy) * Rmax, l, row);
+                if ((uint32_t)(cs + 1) != ((cpred >> (5 * pp)) & 31u))
+                    slab_select(sh, ld, cs, uz, l, &sh.selq[ld], st);
+            }
+        }
+        __syncthreads();
+
+        // --- the flips: four threads per domain, the flipped site (and its spin
+        // word and face copies) and its two neighbours along each axis.  A
+        // neighbour inside the octant takes its class from the words in LDS (the
+        // flipped site still reads its old spin there); one across a face reads
+        // its own neighbours from memory (none of them flips in this cycle).
+        {
+            const uint32_t ld = (uint32_t)tid >> 2;
+            const int part = tid & 3;
+            const uint32_t f = ld < nvalid ? sh.selq[ld] : kNoEvent;
+            if (f != kNoEvent) {
+                const int cs = (int)(f >> 12);
+                const uint32_t q = f & 0xFFFu;
+                const int lx = (int)(q & 15u), ly = (int)((q >> 4) & 15u), lz = (int)(q >> 8);
+                const uint32_t up = cs >= 7;
+                const uint32_t k = kbase + ld;
+                if (part == 0) {
+                    slab_move_lds(sh.sc[ld], cs, site_class(!up, up ? cs - 7 : 6 - cs), lz >> 2);
+                    flip_site<16>(g, k, s, q);
+                    myF += 1;
+                    mydM += up ? -2 : 2;
+                    mydB += 12 - 4 * (long long)(cs % 7);
+                } else {
+                    // axis part - 1 as a unit vector, and the two axes across it
+                    const int ex = part == 1, ey = part == 2, ez = part == 3;
+                    const int ux1 = !ex, uy1 = ex, uz1 = 0;   // y for the x axis, else x
+                    const int ux2 = 0, uy2 = ez, uz2 = !ez;   // y for the z axis, else z
+                    const int dn = up ? -1 : 1;  // change of the neighbours' up counts
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const int side = e ? 1 : -1;
+                        const int x = lx + side * ex, y = ly + side * ey, z = lz + side * ez;
+                        const int along = ex ? x : ey ? y : z;
+                        if ((unsigned)along < 16u) {
+                            const int c_old = slab_class_lds(sh.oct[ld], x, y, z);
+                            const int up_j = c_old >= 7;
+                            slab_move_lds(sh.sc[ld], c_old, site_class(up_j, (up_j ? c_old - 7 : 6 - c_old) + dn),
+                                          z >> 2);
+                        } else {
+                            // across a face: the site and its other five neighbours from memory
+                            const DomainCoord dc = dcoord(k, g.nd);
+                            const int X = (s & 1) * 16 + x, Y = ((s >> 1) & 1) * 16 + y, Z = ((s >> 2) & 1) * 16 + z;
+                            uint32_t kj, kt;
+                            int oj, ot, lzj, lzt;
+                            const uint32_t sj = spin_at16(g, dc, X, Y, Z, kj, oj, lzj);
+                            int nup = (int)up;  // the flipped site, before its flip
+                            nup += (int)spin_at16(g, dc, X + side * ex, Y + side * ey, Z + side * ez, kt, ot, lzt);
+                            nup += (int)spin_at16(g, dc, X - ux1, Y - uy1, Z - uz1, kt, ot, lzt);
+                            nup += (int)spin_at16(g, dc, X + ux1, Y + uy1, Z + uz1, kt, ot, lzt);
+                            nup += (int)spin_at16(g, dc, X - ux2, Y - uy2, Z - uz2, kt, ot, lzt);
+                            nup += (int)spin_at16(g, dc, X + ux2, Y + uy2, Z + uz2, kt, ot, lzt);
+                            slab_move_dev(g.sc + ((uint64_t)kj * 8 + (uint32_t)oj) * kSlabWords, site_class(sj, nup),
+                                          site_class(sj, nup + dn), lzj >> 2);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // the active octants' counts back to memory (lane c of a row: class c)
+#pragma unroll
+        for (int pp = 0; pp < P; ++pp) {
+            const uint32_t ld = (uint32_t)(pp * rows + row);
+            if (ld < nvalid && l < 14) {
+                const uint64_t v = (uint64_t)sh.sc[ld][2 * l] | ((uint64_t)sh.sc[ld][2 * l + 1] << 32);
+                st64(reinterpret_cast<uint64_t *>(g.sc + ((uint64_t)(kbase + ld) * 8 + (uint32_t)s) * kSlabWords +
+                                                  2 * l),
+                     v);
+            }
+        }
+        // this thread's flips, count moves and stores complete
+        __builtin_amdgcn_s_waitcnt(0);
+
+        // --- step 5: the clock
+        {
+            double dt = lnu / (8.0 * Rmax);
+            t = t + dt;
+        }
+        lnu = -log(cycle_draw(g.seed, n + 1, false).ut);
+        __syncthreads();
+
+        const bool last = n + 1 == n_end;
+        const bool record = n + 1 == next_rec && g.rec_cap;
+        if (n + 1 == next_rec) next_rec += obs_every;
+        if (record || last) {
+            long long F = myF, dM = mydM, dB = mydB;
+            for (int o = 32; o > 0; o >>= 1) {
+                F += __shfl_xor(F, o);
+                dM += __shfl_xor(dM, o);
+                dB += __shfl_xor(dB, o);
+            }
+            if ((tid & 63) == 0) {
+                sh.red[0][tid >> 6] = F;
+                sh.red[1][tid >> 6] = dM;
+                sh.red[2][tid >> 6] = dB;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                F = dM = dB = 0;
+                for (int w = 0; w < (nthr >> 6); ++w) {
+                    F += sh.red[0][w];
+                    dM += sh.red[1][w];
+                    dB += sh.red[2][w];
+                }
+                if (last) {
+                    atomicAdd((unsigned long long *)&st->fired, (unsigned long long)F);
+                    atomicAdd((unsigned long long *)&st->nulls,
+                              (unsigned long long)((long long)nvalid * (long long)ncycles - F));
+                    atomicAdd((unsigned long long *)&st->M, (unsigned long long)dM);
+                    atomicAdd((unsigned long long *)&st->B, (unsigned long long)dB);
+                } else {
+                    const uint32_t bankr = rec_index % kRecBanks;
+                    int64_t *rp = xs.recp + (uint64_t)bankr * G * 3;
+                    st64((uint64_t *)&rp[3 * gid], (uint64_t)F);
+                    st64((uint64_t *)&rp[3 * gid + 1], (uint64_t)dM);
+                    st64((uint64_t *)&rp[3 * gid + 2], (uint64_t)dB);
+                    if (recorder) {
+                        const uint32_t slot = sh.pend_tail % kRecBanks;
+                        sh.pend_cycle[slot] = n + 1;
+                        sh.pend_t[slot] = t;
+                        sh.pend_bank[slot] = bankr;
+                        sh.pend_tail += 1;
+                    }
+                }
+            }
+            if (record && !last) rec_index += 1;
+        }
+        if (tid == 0) {
+            if (record || last) __builtin_amdgcn_s_waitcnt(0);
+            st64(&xs.flag[gid], n + 1);
+        }
+    }
+
+    // end of the launch: workgroup 0 waits for every workgroup, then appends the
+    // pending records and the record of the last cycle
+    if (recorder) {
+        if (tid < 64 && !sh.abort) {
+            uint64_t start = now_ticks();
+            for (uint32_t w = tid; w < G; w += 64)
+                while (ld64(&xs.flag[w]) < n_end) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
+                        atomicOr(&st->error, kErrFlagTimeout);
+                        sh.abort = 1;
+                        break;
+                    }
+                }
+        }
+        __syncthreads();
+        if (tid < 64 && !sh.abort) {
+            while (sh.pend_head != sh.pend_tail) {
+                emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (tid == 0) {
+                st->t = t;
+                st->cycle = n_end;
+                if (obs_every && (n_end % obs_every) == 0 && g.rec_cap) {
+                    spkmc_record r;
+                    r.cycle = n_end;
+                    r.fired = ld64(&st->fired);
+                    r.nulls = ld64(&st->nulls);
+                    r.t = t;
+                    r.M = (int64_t)ld64((const uint64_t *)&st->M);
+                    r.B = (int64_t)ld64((const uint64_t *)&st->B);
+                    g.rec[st->rec_count % g.rec_cap] = r;
+                    st->rec_count += 1;
+                }
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kSlabBlock) k_slab(Replica R) {
+    __shared__ SlabShared sh;
+    slab_body<kSlabBlock>(R, blockIdx.x, sh);
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 // Launch shapes.  A 16-lane row owns a domain; a workgroup runs `rows` rows
@@ -1648,6 +2239,29 @@ hipError_t launch_cycle_rows(const Geom &g, uint64_t n, hipStream_t stream) {
     return g.h == 16 ? launch_rows<16, 512, kRowsPasses>(g, n, stream) : launch_rows<8, 1024, kRowsPasses>(g, n, stream);
 }
 
+bool slab_supported(const Geom &g, const spkmc_params &p, std::string &why) {
+    if (g.layout != SPKMC_LAYOUT_PACKED || g.h != 16) { why = "needs the PACKED layout and domain 32"; return false; }
+    if (p.variant) { why = "runs variant 0 only"; return false; }
+    if (g.N / 8 >= (1ull << 31)) { why = "needs fewer than 2^34 sites"; return false; }
+    if (p.wg_domains && p.wg_domains != (int)kSlabDomains) { why = "takes 128 domains per workgroup"; return false; }
+    return true;
+}
+
+hipError_t slab_configure(const Geom &g, int &grid, int &block, int &wg_domains) {
+    int dev = 0, cus = 0, occ = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(&k_slab), kSlabBlock, 0);
+    if (e != hipSuccess) return e;
+    const uint64_t G = ((uint64_t)g.K + kSlabDomains - 1) / kSlabDomains;
+    if (occ <= 0 || G > (uint64_t)occ * cus || G > (uint64_t)kMaxGrid) return hipErrorCooperativeLaunchTooLarge;
+    grid = (int)G;
+    block = kSlabBlock;
+    wg_domains = (int)kSlabDomains;
+    return hipSuccess;
+}
+
 uint64_t persistent_scratch_words(uint64_t K) { return kScratchWordsPerWg * (K / 16 + 2) + 16; }
 
 PersistScratch scratch_of(const Geom &g, int G) {
@@ -1682,6 +2296,28 @@ hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint3
     R.pad = 0;
     void *args[] = {&R};
     return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(block), args, 0, stream);
+}
+
+hipError_t launch_slab(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid,
+                       hipStream_t stream) {
+    if (!g.sc || g.h != 16) return hipErrorInvalidValue;
+    PersistScratch xs = scratch_of(g, grid);
+    hipLaunchKernelGGL(k_persistent_prep, dim3((uint32_t)((grid + 255) / 256)), dim3(256), 0, stream, xs,
+                       (uint32_t)grid, n0, g.dh, (uint64_t)0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    Replica R;
+    R.g = g;
+    R.xs = xs;
+    R.n0 = n0;
+    R.ncycles = ncycles;
+    R.obs_every = obs_every;
+    R.first_wg = 0;
+    R.G = (uint32_t)grid;
+    R.pad = 0;
+    void *args[] = {&R};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_slab), dim3(grid), dim3(kSlabBlock), args, 0,
+                                      stream);
 }
 
 // ---------------------------------------------------------------------------

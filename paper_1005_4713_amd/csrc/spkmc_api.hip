@@ -50,7 +50,7 @@ static int make_rates(const spkmc_params *p, double out[14]) {
 }
 
 struct LayoutPlan {
-    size_t off_rates, off_rec, off_Rk, off_hist, off_flip, off_sync, off_dh, off_spin, off_F, total, spin_bytes;
+    size_t off_rates, off_rec, off_Rk, off_hist, off_flip, off_sync, off_dh, off_sc, off_spin, off_F, total, spin_bytes;
 };
 
 static bool validate(const spkmc_params *p, std::string &why) {
@@ -71,7 +71,7 @@ static bool validate(const spkmc_params *p, std::string &why) {
     if (p->rates != SPKMC_RATES_GLAUBER && p->rates != SPKMC_RATES_METROPOLIS) { why = "unknown rates"; return false; }
     if (p->init < 0 || p->init > 2) { why = "unknown init"; return false; }
     if (p->layout != SPKMC_LAYOUT_INT8 && p->layout != SPKMC_LAYOUT_PACKED) { why = "unknown layout"; return false; }
-    if (p->engine < 0 || p->engine > 3) { why = "unknown engine"; return false; }
+    if (p->engine < 0 || p->engine > 4) { why = "unknown engine"; return false; }
     if (p->wg_domains < 0) { why = "wg_domains must be >= 0"; return false; }
     int h = p->domain / 2;
     if (p->layout == SPKMC_LAYOUT_PACKED && (h % 4)) { why = "PACKED layout needs the octant edge (domain/2) to be a multiple of 4"; return false; }
@@ -98,6 +98,9 @@ static LayoutPlan plan(const spkmc_params *p) {
     lp.off_sync = o; o = align256(o + persistent_scratch_words(lines) * 8);
     lp.off_dh = o;
     if (p->layout == SPKMC_LAYOUT_PACKED) o = align256(o + K * 16 * 8);
+    // slab engine: 28 words of slab class counts per octant (PACKED, h = 16)
+    lp.off_sc = o;
+    if (p->layout == SPKMC_LAYOUT_PACKED && h == 16) o = align256(o + K * 8 * 28 * 4);
     lp.off_spin = o;
     if (p->layout == SPKMC_LAYOUT_INT8) {
         o = align256(o + N);
@@ -191,6 +194,7 @@ spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, 
     g.flip = (uint64_t *)(c->dev + lp.off_flip);
     g.sync = (uint64_t *)(c->dev + lp.off_sync);
     g.dh = p->layout == SPKMC_LAYOUT_PACKED ? (uint64_t *)(c->dev + lp.off_dh) : nullptr;
+    g.sc = p->layout == SPKMC_LAYOUT_PACKED && g.h == 16 ? (uint32_t *)(c->dev + lp.off_sc) : nullptr;
     if (p->layout == SPKMC_LAYOUT_INT8) {
         g.spin8 = (int8_t *)(c->dev + lp.off_spin);
     } else {
@@ -213,6 +217,14 @@ spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, 
     // all-octant R_max (its histograms of every octant stay resident), else the
     // re-binning persistent engine, else the per-cycle engine
     std::string pwhy;
+    if (p->engine == SPKMC_ENGINE_SLAB) {
+        if (!slab_supported(g, *p, pwhy)) return fail(c, SPKMC_E_UNSUPPORTED, "slab engine: " + pwhy);
+        c->engine = SPKMC_ENGINE_SLAB;
+        hipError_t e = slab_configure(g, c->grid, c->block, c->wg_domains);
+        if (e == hipErrorCooperativeLaunchTooLarge)
+            return fail(c, SPKMC_E_UNSUPPORTED, "slab engine: the domains do not fit in one resident launch");
+        if (e != hipSuccess) return hip_fail(c, e, "slab_configure");
+    } else {
     const bool want_inc = p->engine == SPKMC_ENGINE_INCREMENTAL ||
                           (p->engine == SPKMC_ENGINE_AUTO && (p->variant & SPKMC_VARIANT_RMAX_ALL));
     bool pers = persistent_supported(g, *p, want_inc, pwhy);
@@ -239,6 +251,7 @@ spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, 
             return hip_fail(c, e, "persistent_configure");
         }
     }
+    }
 
     hipError_t e;
     if ((e = hipMemsetAsync(c->dev, 0, lp.off_spin, c->stream)) != hipSuccess) return hip_fail(c, e, "hipMemsetAsync");
@@ -255,7 +268,11 @@ spkmc_status spkmc_run(spkmc_ctx *c, uint64_t ncycles, uint32_t obs_every) {
     if (c->failed || !c->dev) return fail(c, SPKMC_E_STATE, "context is in a failed state");
     if (ncycles == 0) return SPKMC_OK;
     hipError_t e = hipSuccess;
-    if (c->engine != SPKMC_ENGINE_CYCLE) {
+    if (c->engine == SPKMC_ENGINE_SLAB) {
+        e = launch_slab(c->g, c->cycle, ncycles, obs_every, c->grid, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "slab kernel launch");
+        c->cycle += ncycles;
+    } else if (c->engine != SPKMC_ENGINE_CYCLE) {
         e = launch_persistent(c->g, c->cycle, ncycles, obs_every, c->grid, c->block, c->wg_domains,
                               c->engine == SPKMC_ENGINE_INCREMENTAL, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "persistent kernel launch");

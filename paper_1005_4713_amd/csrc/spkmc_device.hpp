@@ -52,6 +52,7 @@ struct Geom {
     uint64_t *flip;        // K flip records
     uint64_t *sync;        // persistent engine: R_max slots, flags, record partials (9 G words)
     uint64_t *dh;          // PACKED: class changes pushed across workgroups, K x 8 octants x 2 spins
+    uint32_t *sc;          // PACKED, h = 16: per octant the class counts of its four 4-plane slabs (28 words)
     int8_t *spin8;         // INT8 spins
     uint32_t *A;           // PACKED spins, octant-major, canonical order inside an octant
     uint32_t *F;           // PACKED face copies: per octant x0, x1, y0, y1, z0, z1 (h^2 bits each)

@@ -16,7 +16,7 @@ OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_RANGE, E_UNSUPPORTED = range(7)
 RATES = {"glauber": 0, "metropolis": 1}
 INITS = {"random": 0, "up": 1, "down": 2}
 LAYOUTS = {"int8": 0, "packed": 1}
-ENGINES = {"auto": 0, "cycle": 1, "persistent": 2, "incremental": 3}
+ENGINES = {"auto": 0, "cycle": 1, "persistent": 2, "incremental": 3, "slab": 4}
 VARIANTS = {"rmax_all": 1, "two_colours": 2, "rmax_bound": 4}
 
 
