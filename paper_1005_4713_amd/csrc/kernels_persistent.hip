@@ -1572,6 +1572,7 @@ struct SlabShared {
     double rk[kSlabDomains];
     uint32_t zbuf[kSlabRows][24];           // binning at launch start: z face words per row
     uint32_t nbdom[kSlabDomains][6];
+    uint32_t dco[kSlabDomains];             // domain coordinates kx | ky << 10 | kz << 20
     uint32_t selq[kSlabDomains];
     double rpred[8];
     double rmax;
@@ -1693,7 +1694,7 @@ __device__ __forceinline__ void slab_select(const SlabShared &sh, uint32_t ld, i
     if (cs >= 0 && rank >= excl && rank < incl) {
         const uint32_t r0 = rank - excl;
         const bool first = r0 < ca;
-        const uint32_t bit = (uint32_t)(first ? nth_set_bit(mk[0], r0) : nth_set_bit(mk[1], r0 - ca));
+        const uint32_t bit = (uint32_t)nth_set_bit(first ? mk[0] : mk[1], first ? r0 : r0 - ca);
         const uint32_t q = (uint32_t)(256 * pz) + 32u * (uint32_t)(wi + (first ? 0 : 1)) + bit;
         *slot = ((uint32_t)cs << 12) | q;
     }
@@ -1765,6 +1766,7 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
         int kc[3] = {c.kx, c.ky, c.kz};
         kc[a] = (dir & 1) ? wrapp(kc[a], g.nd) : wrapm(kc[a], g.nd);
         sh.nbdom[ldm][dir] = dindex(kc[0], kc[1], kc[2], g.nd);
+        if (dir == 0) sh.dco[ldm] = (uint32_t)c.kx | ((uint32_t)c.ky << 10) | ((uint32_t)c.kz << 20);
     }
     __syncthreads();
     for (uint32_t i = tid; i < nvalid * 6; i += nthr) {
@@ -1806,6 +1808,9 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
 
     for (uint64_t n = n0; n < n_end; ++n) {
         const int s = cycle_draw(g.seed, n, false).colour;
+        // the same colour again: the octants, halos and counts in LDS are current
+        // (only this workgroup's own flips touched them, patched in below)
+        const bool same = n > n0 && s == prev_colour;
         // step 6 of the previous cycle: the flips (and count moves) that octant s can see
         if (n > n0) {
             int diff = s ^ prev_colour;
@@ -1820,8 +1825,11 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
         // --- step 1 from the counts: the slab counts of the active octants first
         // (the frequency lines need only them), then their words and halos (only
         // the selection needs them: staged into LDS pass by pass just before it)
+        // The counts go out with the first pass's words only; the other passes'
+        // words follow once the counts are in, and arrive while the first
+        // passes select.
         Raw<16> raw[P];
-        {
+        if (!same) {
             uint32_t scw[P][2];
 #pragma unroll
             for (int pp = 0; pp < P; ++pp) {
@@ -1834,12 +1842,8 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
                 scw[pp][0] = v[0];
                 scw[pp][1] = v[1];
             }
-#pragma unroll
-            for (int pp = 0; pp < P; ++pp) {
-                const uint32_t ld = (uint32_t)(pp * rows + row);
-                const bool valid = ld < nvalid;
-                load_octant<16>(g, kbase + ld, s, valid, l, sh.nbdom[valid ? ld : 0], raw[pp]);
-            }
+            load_octant<16>(g, kbase + (uint32_t)row, s, (uint32_t)row < nvalid, l,
+                            sh.nbdom[(uint32_t)row < nvalid ? row : 0], raw[0]);
 #pragma unroll
             for (int pp = 0; pp < P; ++pp) {
                 const uint32_t ld = (uint32_t)(pp * rows + row);
@@ -1848,6 +1852,26 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
                     sh.sc[ld][2 * l + 1] = scw[pp][1];
                     sh.cnt[ld][l] = (scw[pp][0] & 0xFFFFu) + (scw[pp][0] >> 16) + (scw[pp][1] & 0xFFFFu) +
                                     (scw[pp][1] >> 16);
+                }
+            }
+            // the previous cycle's count moves and stores are complete before this
+            // workgroup's next R_max slot goes out (they are old by now)
+            __builtin_amdgcn_s_waitcnt(0);
+            asm volatile("" ::: "memory");  // the other passes' loads after the counts are in
+#pragma unroll
+            for (int pp = 1; pp < P; ++pp) {
+                const uint32_t ld = (uint32_t)(pp * rows + row);
+                const bool valid = ld < nvalid;
+                load_octant<16>(g, kbase + ld, s, valid, l, sh.nbdom[valid ? ld : 0], raw[pp]);
+            }
+        } else {
+            __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+            for (int pp = 0; pp < P; ++pp) {
+                const uint32_t ld = (uint32_t)(pp * rows + row);
+                if (l < 14) {
+                    const uint32_t v0 = sh.sc[ld][2 * l], v1 = sh.sc[ld][2 * l + 1];
+                    sh.cnt[ld][l] = (v0 & 0xFFFFu) + (v0 >> 16) + (v1 & 0xFFFFu) + (v1 >> 16);
                 }
             }
         }
@@ -1885,22 +1909,34 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
             for (int pp = 0; pp < P; ++pp) {
                 const uint32_t ld = (uint32_t)(pp * rows + row);
                 // this row's octant into LDS (the row's own lanes read it back)
-                uint32_t *o = sh.oct[ld];
+                if (!same) {
+                    uint32_t *o = sh.oct[ld];
 #pragma unroll
-                for (int w = 0; w < 8; ++w) o[8 * l + w] = raw[pp].W[w];
-                if (!(l & 1)) {
-                    o[kFxm + (l >> 1)] = raw[pp].xm;
-                    o[kFxp + (l >> 1)] = raw[pp].xp;
-                    o[kFym + (l >> 1)] = raw[pp].ym;
-                    o[kFyp + (l >> 1)] = raw[pp].yp;
+                    for (int w = 0; w < 8; ++w) o[8 * l + w] = raw[pp].W[w];
+                    if (!(l & 1)) {
+                        o[kFxm + (l >> 1)] = raw[pp].xm;
+                        o[kFxp + (l >> 1)] = raw[pp].xp;
+                        o[kFym + (l >> 1)] = raw[pp].ym;
+                        o[kFyp + (l >> 1)] = raw[pp].yp;
+                    }
+                    o[kFzm + l] = raw[pp].zw;  // lanes 8 .. 15: the face above
                 }
-                o[kFzm + l] = raw[pp].zw;  // lanes 8 .. 15: the face above
                 const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
                 const int cs = row_class(sh.acc[ld], ld < nvalid, unit53(ux, uy) * Rspec, l, row);
                 cpred |= (uint32_t)(cs + 1) << (5 * pp);
                 slab_select(sh, ld, cs, uz, l, &sh.selq[ld], st);
             }
         }
+        // the next cycle's draw (-ln u of its clock step, its colour), while the maxima travel
+        const CycleDraw next_draw = cycle_draw(g.seed, n + 1, false);
+        const double lnu_next = -log(next_draw.ut);
+        // a neighbour reads this cycle's flips next cycle only if the next colour
+        // differs from this one in one bit; otherwise they need only be complete
+        // before the next R_max slot goes out (the wait before the next loads)
+        const int next_diff = next_draw.colour ^ s;
+        const bool last = n + 1 == n_end;
+        const bool record = n + 1 == next_rec && g.rec_cap;
+        const bool publish_flag = last || record || (next_diff && !(next_diff & (next_diff - 1)));
         if (tid < 64) {
             if (recorder && sh.pend_head != sh.pend_tail && sh.pend_cycle[sh.pend_head % kRecBanks] + 2 <= n + 1)
                 emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
@@ -1978,41 +2014,93 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
                 } else {
                     // axis part - 1 as a unit vector, and the two axes across it
                     const int ex = part == 1, ey = part == 2, ez = part == 3;
-                    const int ux1 = !ex, uy1 = ex, uz1 = 0;   // y for the x axis, else x
-                    const int ux2 = 0, uy2 = ez, uz2 = !ez;   // y for the z axis, else z
-                    const int dn = up ? -1 : 1;  // change of the neighbours' up counts
+                    const int ux1 = !ex, uy1 = ex;  // y for the x axis, else x
+                    const int uy2 = ez, uz2 = !ez;  // y for the z axis, else z
+                    const int dn = up ? -1 : 1;     // change of the neighbours' up counts
+                    const uint32_t dc = sh.dco[ld];
+                    const DomainCoord c = {(int)(dc & 1023u), (int)((dc >> 10) & 1023u), (int)(dc >> 20)};
+                    const int endA = (int)(g.N / 8u);
+                    const __amdgpu_buffer_rsrc_t A =
+                        __builtin_amdgcn_make_buffer_rsrc((void *)g.A, (short)0, endA, 0x00020000);
+                    // gather: a neighbour across a face reads its spin and its other five
+                    // neighbours from memory (none of them flips in this cycle), both
+                    // neighbours' reads in flight together; one inside the octant reads LDS
+                    uint32_t wv[2][6];
+                    int bitp[2][6], cls[2], slab[2];
+                    bool across[2];
+                    uint32_t kj[2];
+                    int oj[2];
 #pragma unroll
                     for (int e = 0; e < 2; ++e) {
                         const int side = e ? 1 : -1;
                         const int x = lx + side * ex, y = ly + side * ey, z = lz + side * ez;
                         const int along = ex ? x : ey ? y : z;
-                        if ((unsigned)along < 16u) {
-                            const int c_old = slab_class_lds(sh.oct[ld], x, y, z);
-                            const int up_j = c_old >= 7;
-                            slab_move_lds(sh.sc[ld], c_old, site_class(up_j, (up_j ? c_old - 7 : 6 - c_old) + dn),
-                                          z >> 2);
-                        } else {
-                            // across a face: the site and its other five neighbours from memory
-                            const DomainCoord dc = dcoord(k, g.nd);
-                            const int X = (s & 1) * 16 + x, Y = ((s >> 1) & 1) * 16 + y, Z = ((s >> 2) & 1) * 16 + z;
-                            uint32_t kj, kt;
-                            int oj, ot, lzj, lzt;
-                            const uint32_t sj = spin_at16(g, dc, X, Y, Z, kj, oj, lzj);
-                            int nup = (int)up;  // the flipped site, before its flip
-                            nup += (int)spin_at16(g, dc, X + side * ex, Y + side * ey, Z + side * ez, kt, ot, lzt);
-                            nup += (int)spin_at16(g, dc, X - ux1, Y - uy1, Z - uz1, kt, ot, lzt);
-                            nup += (int)spin_at16(g, dc, X + ux1, Y + uy1, Z + uz1, kt, ot, lzt);
-                            nup += (int)spin_at16(g, dc, X - ux2, Y - uy2, Z - uz2, kt, ot, lzt);
-                            nup += (int)spin_at16(g, dc, X + ux2, Y + uy2, Z + uz2, kt, ot, lzt);
-                            slab_move_dev(g.sc + ((uint64_t)kj * 8 + (uint32_t)oj) * kSlabWords, site_class(sj, nup),
-                                          site_class(sj, nup + dn), lzj >> 2);
+                        across[e] = (unsigned)along > 15u;
+                        const int X = (s & 1) * 16 + x, Y = ((s >> 1) & 1) * 16 + y, Z = ((s >> 2) & 1) * 16 + z;
+                        const int PX[6] = {X, X + side * ex, X - ux1, X + ux1, X, X};
+                        const int PY[6] = {Y, Y + side * ey, Y - uy1, Y + uy1, Y - uy2, Y + uy2};
+                        const int PZ[6] = {Z, Z + side * ez, Z, Z, Z - uz2, Z + uz2};
+#pragma unroll
+                        for (int i = 0; i < 6; ++i) {
+                            const int px = PX[i], py = PY[i], pz = PZ[i];
+                            const int cx = px < 0 ? wrapm(c.kx, g.nd) : px >= 32 ? wrapp(c.kx, g.nd) : c.kx;
+                            const int cy = py < 0 ? wrapm(c.ky, g.nd) : py >= 32 ? wrapp(c.ky, g.nd) : c.ky;
+                            const int cz = pz < 0 ? wrapm(c.kz, g.nd) : pz >= 32 ? wrapp(c.kz, g.nd) : c.kz;
+                            const int mx = px & 31, my = py & 31, mz = pz & 31;
+                            const int o = (mx >> 4) | ((my >> 4) << 1) | ((mz >> 4) << 2);
+                            const uint32_t kk = dindex(cx, cy, cz, g.nd);
+                            const uint32_t qq = (uint32_t)((mx & 15) + 16 * ((my & 15) + 16 * (mz & 15)));
+                            const int off = across[e] ? (int)(((kk * 8u + (uint32_t)o) * 128u + (qq >> 5)) * 4u) : endA;
+                            wv[e][i] = __builtin_amdgcn_raw_buffer_load_b32(A, off, 0, kCoherent);
+                            bitp[e][i] = (int)(qq & 31u);
+                            if (i == 0) {
+                                kj[e] = kk;
+                                oj[e] = o;
+                                slab[e] = across[e] ? (mz & 15) >> 2 : z >> 2;
+                            }
                         }
+                        // inside the octant: the class from LDS (a site inside stands in when across)
+                        cls[e] = slab_class_lds(sh.oct[ld], across[e] ? lx : x, across[e] ? ly : y, across[e] ? lz : z);
+                    }
+                    // every read consumed before the first count move goes out
+                    int c_new[2];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const uint32_t sj = (wv[e][0] >> bitp[e][0]) & 1u;
+                        int nup = (int)up;  // the flipped site, before its flip
+#pragma unroll
+                        for (int i = 1; i < 6; ++i) nup += (int)((wv[e][i] >> bitp[e][i]) & 1u);
+                        const int up_j = cls[e] >= 7;
+                        const int nup_in = (up_j ? cls[e] - 7 : 6 - cls[e]);
+                        cls[e] = across[e] ? site_class(sj, nup) : cls[e];
+                        c_new[e] = across[e] ? site_class(sj, nup + dn) : site_class(up_j, nup_in + dn);
+                    }
+                    // (the classes pinned here: no count move may go out before both are known)
+                    asm volatile("" ::"v"(cls[0]), "v"(cls[1]), "v"(c_new[0]), "v"(c_new[1]) : "memory");
+                    // scatter: the class moves
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        if (across[e])
+                            slab_move_dev(g.sc + ((uint64_t)kj[e] * 8 + (uint32_t)oj[e]) * kSlabWords, cls[e],
+                                          c_new[e], slab[e]);
+                        else
+                            slab_move_lds(sh.sc[ld], cls[e], c_new[e], slab[e]);
                     }
                 }
             }
         }
+        // this thread's flips and count moves complete (the flag below publishes them)
+        if (publish_flag) __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        // the active octants' counts back to memory (lane c of a row: class c)
+        // the flipped spins into the octants in LDS (read again if the colour repeats)
+        if ((uint32_t)tid < nvalid && sh.selq[tid] != kNoEvent) {
+            const uint32_t q = sh.selq[tid] & 0xFFFu;
+            sh.oct[tid][q >> 5] ^= 1u << (q & 31);
+        }
+        // the active octants' counts back to memory (lane c of a row: class c).
+        // Only this workgroup reads them, at the start of a later cycle, and no
+        // other workgroup moves them before this workgroup's next R_max slot is
+        // out: the wait for these stores sits before the next cycle's loads.
 #pragma unroll
         for (int pp = 0; pp < P; ++pp) {
             const uint32_t ld = (uint32_t)(pp * rows + row);
@@ -2023,19 +2111,14 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
                      v);
             }
         }
-        // this thread's flips, count moves and stores complete
-        __builtin_amdgcn_s_waitcnt(0);
-
         // --- step 5: the clock
         {
             double dt = lnu / (8.0 * Rmax);
             t = t + dt;
         }
-        lnu = -log(cycle_draw(g.seed, n + 1, false).ut);
+        lnu = lnu_next;
         __syncthreads();
 
-        const bool last = n + 1 == n_end;
-        const bool record = n + 1 == next_rec && g.rec_cap;
         if (n + 1 == next_rec) next_rec += obs_every;
         if (record || last) {
             long long F = myF, dM = mydM, dB = mydB;
@@ -2080,7 +2163,7 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
             }
             if (record && !last) rec_index += 1;
         }
-        if (tid == 0) {
+        if (tid == 0 && publish_flag) {
             if (record || last) __builtin_amdgcn_s_waitcnt(0);
             st64(&xs.flag[gid], n + 1);
         }
