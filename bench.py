@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--zeff-tmax", type=float, default=400.0, help="zeff: simulated time to reach")
     ap.add_argument("--replicas", type=int, default=256, help="batch / serve: lattices in the replica mix")
     ap.add_argument("--cycles", type=int, default=1000, help="batch / serve: cycles per lattice")
-    ap.add_argument("--macro-cycles", type=int, default=100, help="serve: cycles per macro-step")
+    ap.add_argument("--macro-cycles", type=int, default=100,
+                    help="serve: cycles per macro-step; batch: cycles per eager or graph macro-step")
     ap.add_argument("--engine", default="auto", choices=["auto", "cycle", "persistent", "incremental", "slab"])
     ap.add_argument("--wg-domains", type=int, default=0)
     ap.add_argument("--obs-every", type=int, default=10)
@@ -315,6 +316,29 @@ def bench_batch(args):
     q1 = [s.state() for s in solo]
     fired_solo = sum(b[1] - a[1] for a, b in zip(q0, q1))
     same = all(a == b for a, b in zip(s1, q1))
+    del solo
+    # macro-steps of `macro` cycles: eager batch launches, then the same steps as
+    # batch graphs captured once and replayed
+    macro = args.macro_cycles
+    timed = {}
+    for kind in ("eager", "graph"):
+        sims = tune.build(specs, plan["domains"])
+        torch.cuda.synchronize()
+        a0 = [s.state() for s in sims]
+        tk = time.perf_counter()
+        if kind == "eager":
+            tune.run_plan(plan, sims, args.cycles, macro=macro)
+        else:
+            graphs = tune.run_plan_graph(plan, sims, args.cycles, macro)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - tk
+        if kind == "graph":
+            for g in graphs:
+                g.close()
+        a1 = [s.state() for s in sims]
+        timed[kind] = {"value": sum(b[1] - a[1] for a, b in zip(a0, a1)) / secs, "seconds": secs,
+                       "bit_identical_to_plain": all(a == b for a, b in zip(a1, q1))}
+        del sims
     out = {"metric": "spin-flip events/s, batched replica mix", "value": fired / dt, "unit": "spin-flip events/s",
            "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "u32+f64",
            "config": {"workload": f"replica_mix_{args.replicas}", "cycles": args.cycles,
@@ -324,6 +348,8 @@ def bench_batch(args):
            "seconds": dt, "attempts_per_s": attempts / dt,
            "plain": {"value": fired_solo / dt_solo, "seconds": dt_solo, "kind": "each lattice alone, in turn"},
            "speedup_vs_plain": (fired / dt) / (fired_solo / dt_solo), "bit_identical_to_plain": same,
+           "macro_steps": {"cycles_per_step": macro, "eager_batches": timed["eager"],
+                           "batch_graphs": timed["graph"]},
            "tuner": table}
     print(json.dumps(out), flush=True)
 

@@ -241,6 +241,28 @@ size_t spkmc_batch_workspace_bytes(size_t n);
 spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
                              int32_t wg_domains, void *dev_workspace, size_t ws_bytes, spkmc_batch_info *info);
 
+/* A batch macro-step captured once into a HIP graph and replayed: the slot and
+ * flag set-up, the persistent batch launch and a kernel that advances every
+ * descriptor's start cycle by its cycle count, so that each replay continues
+ * every lattice where the last one stopped, with no host work per replay.
+ * Arguments as for spkmc_run_batch; dev_workspace (spkmc_batch_workspace_bytes(n)
+ * bytes, caller-owned) holds the descriptors for the graph's whole life and
+ * must stay untouched until the graph is destroyed and its last replay has
+ * finished.  Nothing runs at creation but the descriptor upload.  While the
+ * graph lives its members advance only through spkmc_batch_graph_launch
+ * (E_STATE from there if a member's cycle count moved otherwise).  Replays are
+ * bit-identical to spkmc_run_batch and to solo runs.  The batch kernel is a
+ * cooperative graph node.  E_UNSUPPORTED if the runtime cannot build or
+ * instantiate the graph. */
+typedef struct spkmc_batch_graph spkmc_batch_graph;
+spkmc_status spkmc_batch_graph_create(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
+                                      int32_t wg_domains, void *dev_workspace, size_t ws_bytes,
+                                      spkmc_batch_info *info, spkmc_batch_graph **out);
+/* Enqueue `replays` replays of the macro-step on the members' stream (async). */
+spkmc_status spkmc_batch_graph_launch(spkmc_batch_graph *graph, uint32_t replays);
+/* Frees the graph (host side and the runtime's graph objects; not the workspace). */
+void spkmc_batch_graph_destroy(spkmc_batch_graph *graph);
+
 /* ------------------------------------------------------------------------- */
 /* Serving: a request loop with continuous batching.                          */
 /* ------------------------------------------------------------------------- */

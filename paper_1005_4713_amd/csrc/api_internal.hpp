@@ -29,6 +29,7 @@ hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t 
                       uint32_t n, int P, Replica *out, int &grid, int &block);
 hipError_t upload_replicas(const Replica *host, uint32_t n, Replica *dev, hipStream_t stream);
 hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipStream_t stream);
+hipError_t capture_batch(Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipGraph_t *graph);
 }  // namespace spkmc
 
 struct spkmc_ctx {

@@ -2480,6 +2480,13 @@ hipError_t upload_replicas(const Replica *host, uint32_t n, Replica *dev, hipStr
     return hipSuccess;
 }
 
+// After a captured macro-step: every lattice's next replay starts where this
+// one stopped.
+__global__ void k_advance_batch(Replica *reps, uint32_t nrep) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nrep) reps[i].n0 += reps[i].ncycles;
+}
+
 // The descriptors must already be in device memory (dev_reps).
 hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipStream_t stream) {
     void *kern = select_kernel(h, P, block, true);
@@ -2490,6 +2497,57 @@ hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int g
     const Replica *reps = dev_reps;
     void *args[] = {&reps, &n};
     return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(block), args, 0, stream);
+}
+
+// One macro-step as a graph of three kernel nodes: the slot and flag set-up,
+// the batch kernel (a cooperative node: every workgroup resident at once, as
+// for hipLaunchCooperativeKernel, which stream capture does not take), and the
+// descriptor advance.  The descriptors must already be in device memory.
+hipError_t capture_batch(Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipGraph_t *graph) {
+    void *kern = select_kernel(h, P, block, true);
+    if (!kern || n == 0) return hipErrorInvalidValue;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    const Replica *creps = dev_reps;
+    Replica *mreps = dev_reps;
+    uint32_t nn = n;
+    int zero = 0;
+    void *a_prep[] = {&creps, &nn, &zero};
+    void *a_batch[] = {&creps, &nn};
+    void *a_adv[] = {&mreps, &nn};
+    hipGraphNode_t nprep = nullptr, nbatch = nullptr, nadv = nullptr;
+    hipKernelNodeParams kp = {};
+    kp.func = reinterpret_cast<void *>(&k_persistent_prep_batch);
+    kp.gridDim = dim3(n < 256 ? n : 256);
+    kp.blockDim = dim3(256);
+    kp.kernelParams = a_prep;
+    e = hipGraphAddKernelNode(&nprep, g, nullptr, 0, &kp);
+    if (e == hipSuccess) {
+        kp.func = kern;
+        kp.gridDim = dim3((uint32_t)grid);
+        kp.blockDim = dim3((uint32_t)block);
+        kp.kernelParams = a_batch;
+        e = hipGraphAddKernelNode(&nbatch, g, &nprep, 1, &kp);
+    }
+    if (e == hipSuccess) {
+        hipKernelNodeAttrValue v = {};
+        v.cooperative = 1;
+        e = hipGraphKernelNodeSetAttribute(nbatch, hipKernelNodeAttributeCooperative, &v);
+    }
+    if (e == hipSuccess) {
+        kp.func = reinterpret_cast<void *>(&k_advance_batch);
+        kp.gridDim = dim3((n + 63) / 64);
+        kp.blockDim = dim3(64);
+        kp.kernelParams = a_adv;
+        e = hipGraphAddKernelNode(&nadv, g, &nbatch, 1, &kp);
+    }
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return e;
+    }
+    *graph = g;
+    return hipSuccess;
 }
 
 }  // namespace spkmc

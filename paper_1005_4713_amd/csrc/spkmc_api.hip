@@ -500,16 +500,25 @@ spkmc_status spkmc_query(const spkmc_ctx *c, spkmc_info *out) {
 
 size_t spkmc_batch_workspace_bytes(size_t n) { return align256(n * replica_bytes()); }
 
-spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
-                             int32_t wg_domains, void *dev_workspace, size_t ws_bytes, spkmc_batch_info *info) {
+}  // extern "C"
+
+// A batch, checked and planned: its members with work, their cycle counts, the
+// host descriptors and the launch shape.
+struct BatchPlan {
+    std::vector<spkmc_ctx *> live;
+    std::vector<uint64_t> nc;
+    std::vector<unsigned char> host;  // the descriptors (replica_bytes() each)
+    hipStream_t stream = nullptr;
+    int h = 0, grid = 0, block = 0, P = 0;
+};
+
+static spkmc_status plan_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
+                               int32_t wg_domains, void *dev_workspace, size_t ws_bytes, BatchPlan &bp) {
     if (!ctxs || !ncycles || n == 0) return fail(nullptr, SPKMC_E_INVAL, "no lattices");
     if (!dev_workspace || ws_bytes < spkmc_batch_workspace_bytes(n))
         return fail(nullptr, SPKMC_E_RANGE, "batch workspace too small");
     std::vector<const Geom *> gs;
-    std::vector<uint64_t> n0, nc;
-    std::vector<spkmc_ctx *> live;
-    hipStream_t stream = nullptr;
-    int h = 0;
+    std::vector<uint64_t> n0;
     for (size_t i = 0; i < n; ++i) {
         spkmc_ctx *c = ctxs[i];
         if (!c) return fail(nullptr, SPKMC_E_INVAL, "NULL context in batch");
@@ -517,19 +526,19 @@ spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *n
         if (ncycles[i] == 0) continue;
         std::string why;
         if (!persistent_supported(c->g, c->p, false, why)) return fail(nullptr, SPKMC_E_UNSUPPORTED, "batch member: " + why);
-        if (live.empty()) {
-            stream = c->stream;
-            h = c->g.h;
-        } else if (c->stream != stream || c->g.h != h) {
+        if (bp.live.empty()) {
+            bp.stream = c->stream;
+            bp.h = c->g.h;
+        } else if (c->stream != bp.stream || c->g.h != bp.h) {
             return fail(nullptr, SPKMC_E_INVAL, "batch members must share the stream and the octant edge");
         }
-        live.push_back(c);
+        bp.live.push_back(c);
         gs.push_back(&c->g);
         n0.push_back(c->cycle);
-        nc.push_back(ncycles[i]);
+        bp.nc.push_back(ncycles[i]);
     }
-    if (live.empty()) return SPKMC_OK;
-    const int rows = persist_rows(h, false), pmax = persist_max_passes(h, false);
+    if (bp.live.empty()) return SPKMC_OK;
+    const int rows = persist_rows(bp.h, false), pmax = persist_max_passes(bp.h, false);
     std::vector<int> Ps;
     if (wg_domains) {
         const int pc = wg_domains / rows;
@@ -540,38 +549,122 @@ spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *n
     } else {
         for (int P = 1; P <= pmax; P <<= 1) Ps.push_back(P);
     }
-    std::vector<unsigned char> host(replica_bytes() * live.size());
-    Replica *reps = reinterpret_cast<Replica *>(host.data());
-    int grid = 0, block = 0, P = 0;
+    bp.host.resize(replica_bytes() * bp.live.size());
+    Replica *reps = reinterpret_cast<Replica *>(bp.host.data());
     hipError_t e = hipErrorCooperativeLaunchTooLarge;
     for (int Pc : Ps) {
-        e = batch_plan(gs.data(), n0.data(), nc.data(), obs_every, (uint32_t)live.size(), Pc, reps, grid, block);
-        if (e == hipSuccess) { P = Pc; break; }
+        e = batch_plan(gs.data(), n0.data(), bp.nc.data(), obs_every, (uint32_t)bp.live.size(), Pc, reps, bp.grid,
+                       bp.block);
+        if (e == hipSuccess) {
+            bp.P = Pc;
+            break;
+        }
     }
     if (e == hipErrorCooperativeLaunchTooLarge)
         return fail(nullptr, SPKMC_E_UNSUPPORTED, "the batch does not fit on the device at once: split it");
     if (e != hipSuccess) return fail(nullptr, SPKMC_E_DEVICE, std::string("batch plan: ") + hipGetErrorString(e));
-    e = upload_replicas(reps, (uint32_t)live.size(), reinterpret_cast<Replica *>(dev_workspace), stream);
+    return SPKMC_OK;
+}
+
+static void batch_info_of(const BatchPlan &bp, spkmc_batch_info *info) {
+    if (!info) return;
+    uint64_t domains = 0;
+    for (spkmc_ctx *c : bp.live) domains += c->g.K;
+    info->grid = bp.grid;
+    info->block = bp.block;
+    info->wg_domains = (bp.block / 16) * bp.P;
+    info->h = bp.h;
+    info->lattices = bp.live.size();
+    info->domains = domains;
+}
+
+struct spkmc_batch_graph {
+    std::vector<spkmc_ctx *> members;
+    std::vector<uint64_t> nc;      // cycles per replay
+    std::vector<uint64_t> expect;  // each member's cycle count when the next replay starts
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
+                             int32_t wg_domains, void *dev_workspace, size_t ws_bytes, spkmc_batch_info *info) {
+    BatchPlan bp;
+    spkmc_status st = plan_batch(ctxs, n, ncycles, obs_every, wg_domains, dev_workspace, ws_bytes, bp);
+    if (st != SPKMC_OK || bp.live.empty()) return st;
+    const uint32_t nl = (uint32_t)bp.live.size();
+    hipError_t e = upload_replicas(reinterpret_cast<const Replica *>(bp.host.data()), nl,
+                                   reinterpret_cast<Replica *>(dev_workspace), bp.stream);
     if (e == hipSuccess)
-        e = launch_batch(reinterpret_cast<const Replica *>(dev_workspace), (uint32_t)live.size(), h, P, grid, block, stream);
+        e = launch_batch(reinterpret_cast<const Replica *>(dev_workspace), nl, bp.h, bp.P, bp.grid, bp.block, bp.stream);
     if (e != hipSuccess) {
-        for (spkmc_ctx *c : live) c->failed = true;
+        for (spkmc_ctx *c : bp.live) c->failed = true;
         return fail(nullptr, SPKMC_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     }
-    uint64_t domains = 0;
-    for (size_t i = 0; i < live.size(); ++i) {
-        live[i]->cycle += nc[i];
-        domains += live[i]->g.K;
+    for (size_t i = 0; i < bp.live.size(); ++i) bp.live[i]->cycle += bp.nc[i];
+    batch_info_of(bp, info);
+    return SPKMC_OK;
+}
+
+spkmc_status spkmc_batch_graph_create(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
+                                      int32_t wg_domains, void *dev_workspace, size_t ws_bytes,
+                                      spkmc_batch_info *info, spkmc_batch_graph **out) {
+    if (!out) return fail(nullptr, SPKMC_E_INVAL, "out is NULL");
+    *out = nullptr;
+    BatchPlan bp;
+    spkmc_status st = plan_batch(ctxs, n, ncycles, obs_every, wg_domains, dev_workspace, ws_bytes, bp);
+    if (st != SPKMC_OK) return st;
+    if (bp.live.empty()) return fail(nullptr, SPKMC_E_INVAL, "no lattice of the batch has cycles to run");
+    const uint32_t nl = (uint32_t)bp.live.size();
+    Replica *dev_reps = reinterpret_cast<Replica *>(dev_workspace);
+    hipError_t e = upload_replicas(reinterpret_cast<const Replica *>(bp.host.data()), nl, dev_reps, bp.stream);
+    if (e != hipSuccess) return fail(nullptr, SPKMC_E_DEVICE, std::string("batch upload: ") + hipGetErrorString(e));
+    auto *gr = new spkmc_batch_graph;
+    gr->members = bp.live;
+    gr->nc = bp.nc;
+    gr->stream = bp.stream;
+    for (spkmc_ctx *c : bp.live) gr->expect.push_back(c->cycle);
+    e = capture_batch(dev_reps, nl, bp.h, bp.P, bp.grid, bp.block, &gr->graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        spkmc_batch_graph_destroy(gr);
+        (void)hipGetLastError();
+        return fail(nullptr, SPKMC_E_UNSUPPORTED, std::string("batch graph: ") + hipGetErrorString(e));
     }
-    if (info) {
-        info->grid = grid;
-        info->block = block;
-        info->wg_domains = (block / 16) * P;
-        info->h = h;
-        info->lattices = live.size();
-        info->domains = domains;
+    batch_info_of(bp, info);
+    *out = gr;
+    return SPKMC_OK;
+}
+
+spkmc_status spkmc_batch_graph_launch(spkmc_batch_graph *gr, uint32_t replays) {
+    if (!gr || !gr->exec) return fail(nullptr, SPKMC_E_INVAL, "graph is NULL");
+    for (size_t i = 0; i < gr->members.size(); ++i) {
+        spkmc_ctx *c = gr->members[i];
+        if (c->failed) return fail(nullptr, SPKMC_E_STATE, "a member of the graph is in a failed state");
+        if (c->cycle != gr->expect[i])
+            return fail(nullptr, SPKMC_E_STATE, "a member of the graph was advanced outside the graph");
+    }
+    for (uint32_t r = 0; r < replays; ++r) {
+        hipError_t e = hipGraphLaunch(gr->exec, gr->stream);
+        if (e != hipSuccess) {
+            for (spkmc_ctx *c : gr->members) c->failed = true;
+            return fail(nullptr, SPKMC_E_DEVICE, std::string("batch graph launch: ") + hipGetErrorString(e));
+        }
+        for (size_t i = 0; i < gr->members.size(); ++i) {
+            gr->members[i]->cycle += gr->nc[i];
+            gr->expect[i] += gr->nc[i];
+        }
     }
     return SPKMC_OK;
+}
+
+void spkmc_batch_graph_destroy(spkmc_batch_graph *gr) {
+    if (!gr) return;
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr;
 }
 
 const char *spkmc_last_error(const spkmc_ctx *c) {

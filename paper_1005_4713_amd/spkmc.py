@@ -73,7 +73,8 @@ SERVE_KEEP = 1
 EXPORTS = ["spkmc_state_bytes", "spkmc_init", "spkmc_run", "spkmc_observables", "spkmc_records",
            "spkmc_copy_spins", "spkmc_set_spins", "spkmc_rate_table", "spkmc_save", "spkmc_load",
            "spkmc_query", "spkmc_last_error", "spkmc_destroy", "spkmc_batch_workspace_bytes",
-           "spkmc_run_batch", "spkmc_server_reserved_bytes", "spkmc_server_create", "spkmc_server_submit",
+           "spkmc_run_batch", "spkmc_batch_graph_create", "spkmc_batch_graph_launch", "spkmc_batch_graph_destroy",
+           "spkmc_server_reserved_bytes", "spkmc_server_create", "spkmc_server_submit",
            "spkmc_server_step", "spkmc_server_poll", "spkmc_server_context", "spkmc_server_release",
            "spkmc_server_clock", "spkmc_server_last_error", "spkmc_server_destroy"]
 
@@ -116,6 +117,13 @@ def _load():
     lib.spkmc_run_batch.restype = C.c_int
     lib.spkmc_run_batch.argtypes = [P(vp), C.c_size_t, P(C.c_uint64), C.c_uint32, C.c_int32, vp, C.c_size_t,
                                     P(BatchInfo)]
+    lib.spkmc_batch_graph_create.restype = C.c_int
+    lib.spkmc_batch_graph_create.argtypes = [P(vp), C.c_size_t, P(C.c_uint64), C.c_uint32, C.c_int32, vp,
+                                             C.c_size_t, P(BatchInfo), P(vp)]
+    lib.spkmc_batch_graph_launch.restype = C.c_int
+    lib.spkmc_batch_graph_launch.argtypes = [vp, C.c_uint32]
+    lib.spkmc_batch_graph_destroy.restype = None
+    lib.spkmc_batch_graph_destroy.argtypes = [vp]
     lib.spkmc_server_reserved_bytes.restype = C.c_size_t
     lib.spkmc_server_reserved_bytes.argtypes = [P(ServerConfig)]
     lib.spkmc_server_create.restype = C.c_int
@@ -297,6 +305,49 @@ def run_batch(sims, ncycles, obs_every=0, wg_domains=0):
     if st != OK:
         raise SpkmcError(st, lib.spkmc_last_error(None).decode())
     return {f: getattr(info, f) for f, _ in BatchInfo._fields_}
+
+
+class BatchGraph:
+    """One batch macro-step (ncycles[i] cycles of each lattice) captured into a
+    HIP graph by the library and replayed with launch(replays); the graph owns
+    its own descriptor workspace (see spkmc_batch_graph_*)."""
+
+    def __init__(self, sims, ncycles, obs_every=0, wg_domains=0):
+        import torch
+        n = len(sims)
+        if isinstance(ncycles, int):
+            ncycles = [ncycles] * n
+        self.sims = list(sims)  # the lattices stay alive with the graph
+        self.ws = torch.empty(max(lib.spkmc_batch_workspace_bytes(n), 1 << 16), dtype=torch.uint8,
+                              device=sims[0].device)
+        ctxs = (C.c_void_p * n)(*[sim.ctx.value for sim in sims])
+        cyc = (C.c_uint64 * n)(*[int(c) for c in ncycles])
+        info = BatchInfo()
+        self.g = C.c_void_p()
+        st = lib.spkmc_batch_graph_create(ctxs, n, cyc, int(obs_every), int(wg_domains),
+                                          C.c_void_p(self.ws.data_ptr()), self.ws.numel(), C.byref(info),
+                                          C.byref(self.g))
+        if st != OK:
+            raise SpkmcError(st, lib.spkmc_last_error(None).decode())
+        self.info = {f: getattr(info, f) for f, _ in BatchInfo._fields_}
+
+    def launch(self, replays=1):
+        st = lib.spkmc_batch_graph_launch(self.g, int(replays))
+        if st != OK:
+            raise SpkmcError(st, lib.spkmc_last_error(None).decode())
+
+    def close(self):
+        if getattr(self, "g", None) and lib is not None:
+            import torch
+            torch.cuda.synchronize(self.ws.device)  # the last replay reads the workspace
+            lib.spkmc_batch_graph_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

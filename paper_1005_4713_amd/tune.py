@@ -89,6 +89,19 @@ def run_plan(plan, sims, ncycles, obs_every=0, macro=None):
             left -= step
 
 
+def run_plan_graph(plan, sims, ncycles, macro, obs_every=0):
+    """The plan's launches as batch graphs of one `macro`-cycle macro-step each,
+    every graph replayed ncycles // macro times (ncycles a multiple of macro);
+    returns the graphs, which the caller closes once the replays are done."""
+    if ncycles % macro:
+        raise ValueError("ncycles must be a multiple of macro")
+    graphs = [spkmc.BatchGraph([sims[i] for i in ln["members"]], macro, obs_every=obs_every,
+                               wg_domains=ln["wg_domains"]) for ln in plan["launches"]]
+    for g in graphs:
+        g.launch(ncycles // macro)
+    return graphs
+
+
 def capacity():
     return torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
 
