@@ -460,7 +460,7 @@ def main():
     kernel = (f"k_persistent<{info['h']}, {info['wg_domains'] * 16 // info['block']}, {info['block']}, "
               f"{str(inc).lower()}, {lpd}>" if launches == 1 else "whole cycle (3 launches)")
     if info["engine"] == spkmc.ENGINES["slab"]:
-        kernel = "k_slab"
+        kernel = f"k_slab<{str(bool(sim.params.variant & spkmc.VARIANTS['rmax_all'])).lower()}>"
     traffic, traffic_rec = (None, None)
     if launches == 1:
         traffic, traffic_rec = measured_traffic(w["name"], kernel, args.variant or "contract", args.steps)

@@ -88,12 +88,12 @@ enum { SPKMC_LAYOUT_INT8 = 0, SPKMC_LAYOUT_PACKED = 1 };
  * stay on chip and follow every flip (the flipped site and its six neighbours
  * change class); a cycle classifies its active octant only to locate the
  * selected site, while the R_max exchange is in flight.
- * SLAB: the persistent launch for octant edge 16 (domain 32), variant 0: the
- * class counts of every octant, split over its four slabs of four z-planes,
- * stay in device memory (state_bytes grows by 896 bytes per domain for PACKED
- * lattices with domain 32) and follow every flip; a cycle reads the counts of
- * its active octant instead of binning it, and classifies only the slab that
- * holds the selected site.
+ * SLAB: the persistent launch for octant edge 16 (domain 32), variants 0 and
+ * RMAX_ALL: the class counts of every octant, split over its four slabs of four
+ * z-planes, stay in device memory (state_bytes grows by 896 bytes per domain
+ * for PACKED lattices with domain 32) and follow every flip; a cycle reads the
+ * counts of its active octant (of every octant with RMAX_ALL) instead of
+ * binning it, and classifies only the slab that holds the selected site.
  * All engines produce bit-identical trajectories. */
 enum { SPKMC_ENGINE_AUTO = 0, SPKMC_ENGINE_CYCLE = 1, SPKMC_ENGINE_PERSISTENT = 2, SPKMC_ENGINE_INCREMENTAL = 3,
        SPKMC_ENGINE_SLAB = 4 };
@@ -111,7 +111,9 @@ enum { SPKMC_ENGINE_AUTO = 0, SPKMC_ENGINE_CYCLE = 1, SPKMC_ENGINE_PERSISTENT = 
  *   taken; more null events, the same dynamics.
  * RMAX_ALL and RMAX_BOUND exclude each other.  Engines: CYCLE runs every
  * variant; PERSISTENT runs every combination of TWO_COLOURS and RMAX_BOUND;
- * INCREMENTAL runs 0 and RMAX_ALL (AUTO picks accordingly). */
+ * INCREMENTAL runs 0 and RMAX_ALL; SLAB runs 0 and RMAX_ALL with domain 32.
+ * AUTO: RMAX_ALL on SLAB where it runs, else on INCREMENTAL; the others on
+ * PERSISTENT where it runs, else on CYCLE. */
 enum { SPKMC_VARIANT_RMAX_ALL = 1, SPKMC_VARIANT_TWO_COLOURS = 2, SPKMC_VARIANT_RMAX_BOUND = 4 };
 
 typedef struct spkmc_params {

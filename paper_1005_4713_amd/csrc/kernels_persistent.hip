@@ -1567,7 +1567,7 @@ struct SlabShared {
     double r[14];
     uint32_t oct[kSlabDomains][kOctLds];    // active octants and their halos
     uint32_t sc[kSlabDomains][kSlabWords];  // slab counts of the active octants
-    uint32_t cnt[kSlabDomains][14];         // class counts of the active octants
+    uint16_t cnt[kSlabDomains][8][14];      // class counts (the active octant; every octant for the all-octant R_max)
     double acc[kSlabDomains][14];           // running FP64 sums of the frequency lines
     double rk[kSlabDomains];
     uint32_t zbuf[kSlabRows][24];           // binning at launch start: z face words per row
@@ -1734,7 +1734,9 @@ __device__ __forceinline__ void slab_bin_octant(const Geom &g, uint32_t kbase, u
     }
 }
 
-template <int BLOCK>
+// ALL: R_max over every octant of every domain (variant A): the counts of all
+// eight octants are read every cycle, and every neighbour is waited for.
+template <int BLOCK, bool ALL>
 __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, SlabShared &sh) {
     static_assert(BLOCK == kSlabBlock, "one launch shape");
     const Geom &g = R.g;
@@ -1810,9 +1812,11 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
         const int s = cycle_draw(g.seed, n, false).colour;
         // the same colour again: the octants, halos and counts in LDS are current
         // (only this workgroup's own flips touched them, patched in below)
-        const bool same = n > n0 && s == prev_colour;
+        const bool same = !ALL && n > n0 && s == prev_colour;
         // step 6 of the previous cycle: the flips (and count moves) that octant s can see
-        if (n > n0) {
+        if (ALL && n > n0) {
+            if (!wait_neighbours<BLOCK>(xs, st, sh, G, -1, n)) break;
+        } else if (n > n0) {
             int diff = s ^ prev_colour;
             if (diff && !(diff & (diff - 1))) {
                 int a = diff == 1 ? 0 : diff == 2 ? 1 : 2;
@@ -1830,17 +1834,26 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
         // passes select.
         Raw<16> raw[P];
         if (!same) {
-            uint32_t scw[P][2];
+            // with ALL this cycle reads back the counts of the previous cycle's
+            // octant, which this workgroup stored: those stores complete first
+            if (ALL) __builtin_amdgcn_s_waitcnt(0);
+            // lane c of a row: class c's slab counts (of every octant with ALL)
+            constexpr int NO = ALL ? 8 : 1;
+            uint32_t scw[P][NO][2];
 #pragma unroll
             for (int pp = 0; pp < P; ++pp) {
                 const uint32_t ld = (uint32_t)(pp * rows + row);
                 const bool valid = ld < nvalid;
-                const int off = valid && l < 14
-                                    ? (int)((((kbase + ld) * 8u + (uint32_t)s) * kSlabWords + 2u * (uint32_t)l) * 4u)
-                                    : endSC;
-                const auto v = __builtin_amdgcn_raw_buffer_load_b64(SC, off, 0, kCoherent);
-                scw[pp][0] = v[0];
-                scw[pp][1] = v[1];
+#pragma unroll
+                for (int oi = 0; oi < NO; ++oi) {
+                    const uint32_t o = ALL ? (uint32_t)oi : (uint32_t)s;
+                    const int off = valid && l < 14
+                                        ? (int)((((kbase + ld) * 8u + o) * kSlabWords + 2u * (uint32_t)l) * 4u)
+                                        : endSC;
+                    const auto v = __builtin_amdgcn_raw_buffer_load_b64(SC, off, 0, kCoherent);
+                    scw[pp][oi][0] = v[0];
+                    scw[pp][oi][1] = v[1];
+                }
             }
             load_octant<16>(g, kbase + (uint32_t)row, s, (uint32_t)row < nvalid, l,
                             sh.nbdom[(uint32_t)row < nvalid ? row : 0], raw[0]);
@@ -1848,10 +1861,16 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
             for (int pp = 0; pp < P; ++pp) {
                 const uint32_t ld = (uint32_t)(pp * rows + row);
                 if (l < 14) {
-                    sh.sc[ld][2 * l] = scw[pp][0];
-                    sh.sc[ld][2 * l + 1] = scw[pp][1];
-                    sh.cnt[ld][l] = (scw[pp][0] & 0xFFFFu) + (scw[pp][0] >> 16) + (scw[pp][1] & 0xFFFFu) +
-                                    (scw[pp][1] >> 16);
+#pragma unroll
+                    for (int oi = 0; oi < NO; ++oi) {
+                        const uint32_t w0 = scw[pp][oi][0], w1 = scw[pp][oi][1];
+                        const int o = ALL ? oi : s;
+                        sh.cnt[ld][o][l] = (uint16_t)((w0 & 0xFFFFu) + (w0 >> 16) + (w1 & 0xFFFFu) + (w1 >> 16));
+                        if (o == s) {
+                            sh.sc[ld][2 * l] = w0;
+                            sh.sc[ld][2 * l + 1] = w1;
+                        }
+                    }
                 }
             }
             // the previous cycle's count moves and stores are complete before this
@@ -1871,19 +1890,38 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
                 const uint32_t ld = (uint32_t)(pp * rows + row);
                 if (l < 14) {
                     const uint32_t v0 = sh.sc[ld][2 * l], v1 = sh.sc[ld][2 * l + 1];
-                    sh.cnt[ld][l] = (v0 & 0xFFFFu) + (v0 >> 16) + (v1 & 0xFFFFu) + (v1 >> 16);
+                    sh.cnt[ld][s][l] = (uint16_t)((v0 & 0xFFFFu) + (v0 >> 16) + (v1 & 0xFFFFu) + (v1 >> 16));
                 }
             }
         }
+        if (ALL && tid < (int)D) sh.rk[tid] = 0.0;
         __syncthreads();
-        for (uint32_t i = tid; i < D; i += nthr) {
-            double a = 0.0;
-            for (int c = 0; c < 14; ++c) {
-                double term = (double)sh.cnt[i][c] * sh.r[c];
-                a = a + term;
-                sh.acc[i][c] = a;
+        if (ALL) {
+            // every octant's frequency line; the active one keeps its running sums,
+            // the domain's largest line goes into rk (non-negative doubles order as
+            // their bit patterns)
+            for (uint32_t i = tid; i < D * 8; i += nthr) {
+                const uint32_t ld = i >> 3;
+                const int o = (int)(i & 7u);
+                double a = 0.0;
+                for (int c = 0; c < 14; ++c) {
+                    double term = (double)sh.cnt[ld][o][c] * sh.r[c];
+                    a = a + term;
+                    if (o == s) sh.acc[ld][c] = a;
+                }
+                if (ld < nvalid)
+                    atomicMax(reinterpret_cast<unsigned long long *>(&sh.rk[ld]), (unsigned long long)double_to_bits(a));
             }
-            sh.rk[i] = i < nvalid ? a : 0.0;
+        } else {
+            for (uint32_t i = tid; i < D; i += nthr) {
+                double a = 0.0;
+                for (int c = 0; c < 14; ++c) {
+                    double term = (double)sh.cnt[i][s][c] * sh.r[c];
+                    a = a + term;
+                    sh.acc[i][c] = a;
+                }
+                sh.rk[i] = i < nvalid ? a : 0.0;
+            }
         }
         __syncthreads();
 
@@ -1936,7 +1974,7 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
         const int next_diff = next_draw.colour ^ s;
         const bool last = n + 1 == n_end;
         const bool record = n + 1 == next_rec && g.rec_cap;
-        const bool publish_flag = last || record || (next_diff && !(next_diff & (next_diff - 1)));
+        const bool publish_flag = ALL || last || record || (next_diff && !(next_diff & (next_diff - 1)));
         if (tid < 64) {
             if (recorder && sh.pend_head != sh.pend_tail && sh.pend_cycle[sh.pend_head % kRecBanks] + 2 <= n + 1)
                 emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
@@ -2209,9 +2247,10 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
     }
 }
 
+template <bool ALL>
 __global__ void __launch_bounds__(kSlabBlock) k_slab(Replica R) {
     __shared__ SlabShared sh;
-    slab_body<kSlabBlock>(R, blockIdx.x, sh);
+    slab_body<kSlabBlock, ALL>(R, blockIdx.x, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -2322,9 +2361,14 @@ hipError_t launch_cycle_rows(const Geom &g, uint64_t n, hipStream_t stream) {
     return g.h == 16 ? launch_rows<16, 512, kRowsPasses>(g, n, stream) : launch_rows<8, 1024, kRowsPasses>(g, n, stream);
 }
 
+static const void *slab_kernel(const Geom &g) {
+    return (g.variant & SPKMC_VARIANT_RMAX_ALL) ? reinterpret_cast<const void *>(&k_slab<true>)
+                                                : reinterpret_cast<const void *>(&k_slab<false>);
+}
+
 bool slab_supported(const Geom &g, const spkmc_params &p, std::string &why) {
     if (g.layout != SPKMC_LAYOUT_PACKED || g.h != 16) { why = "needs the PACKED layout and domain 32"; return false; }
-    if (p.variant) { why = "runs variant 0 only"; return false; }
+    if (p.variant & ~(uint32_t)SPKMC_VARIANT_RMAX_ALL) { why = "runs variants 0 and RMAX_ALL"; return false; }
     if (g.N / 8 >= (1ull << 31)) { why = "needs fewer than 2^34 sites"; return false; }
     if (p.wg_domains && p.wg_domains != (int)kSlabDomains) { why = "takes 128 domains per workgroup"; return false; }
     return true;
@@ -2335,7 +2379,7 @@ hipError_t slab_configure(const Geom &g, int &grid, int &block, int &wg_domains)
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(&k_slab), kSlabBlock, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, slab_kernel(g), kSlabBlock, 0);
     if (e != hipSuccess) return e;
     const uint64_t G = ((uint64_t)g.K + kSlabDomains - 1) / kSlabDomains;
     if (occ <= 0 || G > (uint64_t)occ * cus || G > (uint64_t)kMaxGrid) return hipErrorCooperativeLaunchTooLarge;
@@ -2399,7 +2443,7 @@ hipError_t launch_slab(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t ob
     R.G = (uint32_t)grid;
     R.pad = 0;
     void *args[] = {&R};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_slab), dim3(grid), dim3(kSlabBlock), args, 0,
+    return hipLaunchCooperativeKernel(slab_kernel(g), dim3(grid), dim3(kSlabBlock), args, 0,
                                       stream);
 }
 

@@ -213,11 +213,17 @@ spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, 
     c->spin_bytes = lp.spin_bytes;
     c->rec_off = lp.off_rec;
 
-    // engine choice: the incremental engine for an explicit request or for the
-    // all-octant R_max (its histograms of every octant stay resident), else the
-    // re-binning persistent engine, else the per-cycle engine
+    // engine choice: the slab engine for an explicit request or (AUTO) the
+    // all-octant R_max with domain 32; the incremental engine for an explicit
+    // request or the all-octant R_max otherwise (its histograms of every octant
+    // stay resident); else the re-binning persistent engine, else the per-cycle
+    // engine
     std::string pwhy;
-    if (p->engine == SPKMC_ENGINE_SLAB) {
+    // AUTO with the all-octant R_max: the slab engine where it runs (PACKED,
+    // domain 32; it reads every octant's counts instead of keeping them on chip)
+    const bool auto_slab = p->engine == SPKMC_ENGINE_AUTO && (p->variant & SPKMC_VARIANT_RMAX_ALL) &&
+                           slab_supported(g, *p, pwhy) && slab_configure(g, c->grid, c->block, c->wg_domains) == hipSuccess;
+    if (p->engine == SPKMC_ENGINE_SLAB || auto_slab) {
         if (!slab_supported(g, *p, pwhy)) return fail(c, SPKMC_E_UNSUPPORTED, "slab engine: " + pwhy);
         c->engine = SPKMC_ENGINE_SLAB;
         hipError_t e = slab_configure(g, c->grid, c->block, c->wg_domains);

@@ -83,4 +83,42 @@ def test_slab_unsupported(spkmc):
     with pytest.raises(spkmc.SpkmcError):
         spkmc.Sim(64, 32, engine="slab", seed=1, variant=2)          # two colours
     with pytest.raises(spkmc.SpkmcError):
+        spkmc.Sim(64, 32, engine="slab", seed=1, variant=4)          # the fixed bound
+    with pytest.raises(spkmc.SpkmcError):
         spkmc.Sim(64, 32, engine="slab", seed=1, layout="int8")
+
+
+@pytest.mark.parametrize("L,kw", [
+    (32, dict()),
+    (64, dict(H=0.05, rates="metropolis")),
+    (128, dict(init="up", T=4.4)),
+    (160, dict(H=-0.05)),
+])
+def test_slab_rmax_all_vs_oracle(spkmc, L, kw):
+    """The all-octant R_max (variant A) from the counts of every octant."""
+    print("case slab rmax_all", L, kw, flush=True)
+    kw.setdefault("T", 4.5115)
+    gpu = spkmc.Sim(L, 32, layout="packed", engine="slab", variant=1, seed=13, record_cap=256, **kw)
+    assert gpu.info()["engine"] == spkmc.ENGINES["slab"]
+    orc = _orc(L, 32, seed=13, rmax_scope=1, **kw)
+    for n in (37, 63, 100):
+        gpu.run(n, obs_every=10)
+        ro = orc.run(n, obs_every=10)
+        rg = gpu.records(len(ro)) if ro else []
+        assert len(rg) == len(ro)
+        for g_, o_ in zip(rg, ro):
+            _same(g_, o_)
+        _same(gpu.state(), orc.state())
+        assert np.array_equal(gpu.spins(), orc.spins())
+    assert orc.check_failures() == 0
+
+
+def test_slab_rmax_all_vs_incremental(spkmc):
+    print("case slab rmax_all vs incremental 512", flush=True)
+    a = spkmc.Sim(512, 32, engine="slab", variant=1, seed=17, record_cap=64)
+    b = spkmc.Sim(512, 32, engine="incremental", variant=1, seed=17, record_cap=64)
+    a.run(150, obs_every=25)
+    b.run(150, obs_every=25)
+    assert a.records() == b.records()
+    assert a.state() == b.state()
+    assert np.array_equal(a.spins(), b.spins())

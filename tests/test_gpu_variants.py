@@ -120,6 +120,8 @@ def test_persistent_two_colours(spkmc, variant, L, d, kw):
 
 def test_auto_engine_choice(spkmc):
     pick = lambda v: spkmc.Sim(64, 16, variant=v, seed=1).info()["engine"]  # noqa: E731
+    assert spkmc.Sim(64, 32, variant=RMAX_ALL, seed=1).info()["engine"] == spkmc.ENGINES["slab"]
+    assert spkmc.Sim(64, 32, seed=1).info()["engine"] == spkmc.ENGINES["persistent"]
     assert pick(0) == spkmc.ENGINES["persistent"]
     assert pick(BOUND) == spkmc.ENGINES["persistent"]
     assert pick(RMAX_ALL) == spkmc.ENGINES["incremental"]
