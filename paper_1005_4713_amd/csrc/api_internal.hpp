@@ -9,10 +9,16 @@ namespace spkmc {
 hipError_t launch_init(const Geom &g, int init, hipStream_t stream);
 hipError_t launch_faces(const Geom &g, hipStream_t stream);
 hipError_t launch_observables(const Geom &g, hipStream_t stream);
-hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream_t stream);
+// slab: the per-cycle slab kernels (their counts binned by launch_slab_bin first)
+hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream_t stream, bool slab);
 // The per-cycle engine's row kernels (PACKED, octant edge 8 or 16, not RMAX_ALL).
 bool rows_supported(const Geom &g);
 hipError_t launch_cycle_rows(const Geom &g, uint64_t n, hipStream_t stream);
+// Per-cycle slab kernels (PACKED, octant edge 16): the counts of every octant
+// once per run, then per cycle the line maximum and the selection with flips.
+bool slab_rows_supported(const Geom &g);
+hipError_t launch_slab_bin(const Geom &g, hipStream_t stream);
+hipError_t launch_cycle_slab(const Geom &g, uint64_t n, hipStream_t stream);
 bool persistent_supported(const Geom &g, const spkmc_params &p, bool inc, std::string &why);
 hipError_t persistent_configure(const Geom &g, const spkmc_params &p, bool inc, int &grid, int &block,
                                 int &wg_domains);

@@ -307,7 +307,15 @@ hipError_t launch_observables(const Geom &g, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream_t stream) {
+hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream_t stream, bool slab) {
+    if (slab) {
+        // PACKED lattices with octant edge 16: the per-cycle slab kernels (their
+        // counts binned at the start of the run), then step 5 here
+        hipError_t e = launch_cycle_slab(g, n, stream);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, stream, g, n, obs_every);
+        return hipGetLastError();
+    }
     if (rows_supported(g)) {
         // PACKED lattices with octant edge 8 or 16: the row kernels, then step 5 here
         hipError_t e = launch_cycle_rows(g, n, stream);

@@ -1643,17 +1643,16 @@ __device__ __forceinline__ void slab_move_dev(uint32_t *sc, int c_old, int c_new
 // the class passes j; lane l of the row classifies words 2 (l & 3) and
 // 2 (l & 3) + 1 of plane 4 slab + l / 4 of that slab, so the lanes run in
 // canonical order.  Every lane of the row takes part.
-__device__ __forceinline__ void slab_select(const SlabShared &sh, uint32_t ld, int cs, uint32_t uz, int l,
+__device__ __forceinline__ void slab_select(const uint32_t *sc, const uint32_t *o, int cs, uint32_t uz, int l,
                                             uint32_t *slot, DevState *st) {
     if (l == 0) *slot = kNoEvent;
     const int c = cs >= 0 ? cs : 0;
-    const uint32_t v0 = sh.sc[ld][2 * c], v1 = sh.sc[ld][2 * c + 1];
+    const uint32_t v0 = sc[2 * c], v1 = sc[2 * c + 1];
     const uint32_t e1 = v0 & 0xFFFFu, e2 = e1 + (v0 >> 16), e3 = e2 + (v1 & 0xFFFFu), ncs = e3 + (v1 >> 16);
     const uint32_t j = cs >= 0 ? mul_index(uz, ncs) : 0u;
     const uint32_t b = (j >= e1 ? 1u : 0u) + (j >= e2 ? 1u : 0u) + (j >= e3 ? 1u : 0u);
     const uint32_t rank = j - (b == 0 ? 0u : b == 1 ? e1 : b == 2 ? e2 : e3);
     const int pz = 4 * (int)b + (l >> 2), wi = 2 * (l & 3);
-    const uint32_t *o = sh.oct[ld];
     const uint32_t wa = o[8 * pz + wi], wb = o[8 * pz + wi + 1];
     // y neighbours: row 2 wi - 1 (the previous word, or the face below) and row
     // 2 wi + 4 (the word after next, or the face above); a face row of plane pz
@@ -1703,8 +1702,8 @@ __device__ __forceinline__ void slab_select(const SlabShared &sh, uint32_t ld, i
 // Bin octant o of every domain of the workgroup into its slab counts in device
 // memory: the 13 moments of each plane (lane), summed over the slab's four
 // lanes, give the slab's histogram.
-__device__ __forceinline__ void slab_bin_octant(const Geom &g, uint32_t kbase, uint32_t nvalid, int o,
-                                                SlabShared &sh) {
+template <class SH>
+__device__ __forceinline__ void slab_bin_octant(const Geom &g, uint32_t kbase, uint32_t nvalid, int o, SH &sh) {
     const int tid = threadIdx.x, row = tid >> 4, l = tid & 15;
 #pragma unroll 1
     for (int pp = 0; pp < kSlabPasses; ++pp) {
@@ -1730,6 +1729,105 @@ __device__ __forceinline__ void slab_bin_octant(const Geom &g, uint32_t kbase, u
         for (int c = 0; c < 14; ++c) {
             const uint32_t lo = dpp0<kRowShr4>(hc[c]);  // lane 4 b + 3 -> 4 b + 7
             if (valid && (l & 7) == 7) st32(dst + 2 * c, lo | (hc[c] << 16));
+        }
+    }
+}
+
+// Part `part` of the flip f = (cs << 12) | q of octant (k, so): part 0 flips the
+// site (its spin word and face copies) and moves its class; parts 1..3 move the
+// classes of its two neighbours along axis part - 1.  A neighbour inside the
+// octant takes its class from the octant and halo in LDS (o; the flipped site
+// still reads its old spin there) and moves in the octant's counts in LDS (sc);
+// one across a face reads its own neighbours from memory (none of them flips in
+// the same cycle) and moves in that octant's counts by device atomics.  dco_k:
+// the coordinates of domain k (kx | ky << 10 | kz << 20).
+__device__ __forceinline__ void slab_flip_part(const Geom &g, const uint32_t *o, uint32_t *sc, uint32_t dco_k,
+                                               uint32_t k, int so, uint32_t f, int part, long long &F,
+                                               long long &dM, long long &dB) {
+    const int cs = (int)(f >> 12);
+    const uint32_t q = f & 0xFFFu;
+    const int lx = (int)(q & 15u), ly = (int)((q >> 4) & 15u), lz = (int)(q >> 8);
+    const uint32_t up = cs >= 7;
+    if (part == 0) {
+        slab_move_lds(sc, cs, site_class(!up, up ? cs - 7 : 6 - cs), lz >> 2);
+        flip_site<16>(g, k, so, q);
+        F += 1;
+        dM += up ? -2 : 2;
+        dB += 12 - 4 * (long long)(cs % 7);
+    } else {
+        // axis part - 1 as a unit vector, and the two axes across it
+        const int ex = part == 1, ey = part == 2, ez = part == 3;
+        const int ux1 = !ex, uy1 = ex;  // y for the x axis, else x
+        const int uy2 = ez, uz2 = !ez;  // y for the z axis, else z
+        const int dn = up ? -1 : 1;     // change of the neighbours' up counts
+        const uint32_t dc = dco_k;
+        const DomainCoord c = {(int)(dc & 1023u), (int)((dc >> 10) & 1023u), (int)(dc >> 20)};
+        const int endA = (int)(g.N / 8u);
+        const __amdgpu_buffer_rsrc_t A =
+            __builtin_amdgcn_make_buffer_rsrc((void *)g.A, (short)0, endA, 0x00020000);
+        // gather: a neighbour across a face reads its spin and its other five
+        // neighbours from memory (none of them flips in this cycle), both
+        // neighbours' reads in flight together; one inside the octant reads LDS
+        uint32_t wv[2][6];
+        int bitp[2][6], cls[2], slab[2];
+        bool across[2];
+        uint32_t kj[2];
+        int oj[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int side = e ? 1 : -1;
+            const int x = lx + side * ex, y = ly + side * ey, z = lz + side * ez;
+            const int along = ex ? x : ey ? y : z;
+            across[e] = (unsigned)along > 15u;
+            const int X = (so & 1) * 16 + x, Y = ((so >> 1) & 1) * 16 + y, Z = ((so >> 2) & 1) * 16 + z;
+            const int PX[6] = {X, X + side * ex, X - ux1, X + ux1, X, X};
+            const int PY[6] = {Y, Y + side * ey, Y - uy1, Y + uy1, Y - uy2, Y + uy2};
+            const int PZ[6] = {Z, Z + side * ez, Z, Z, Z - uz2, Z + uz2};
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                const int px = PX[i], py = PY[i], pz = PZ[i];
+                const int cx = px < 0 ? wrapm(c.kx, g.nd) : px >= 32 ? wrapp(c.kx, g.nd) : c.kx;
+                const int cy = py < 0 ? wrapm(c.ky, g.nd) : py >= 32 ? wrapp(c.ky, g.nd) : c.ky;
+                const int cz = pz < 0 ? wrapm(c.kz, g.nd) : pz >= 32 ? wrapp(c.kz, g.nd) : c.kz;
+                const int mx = px & 31, my = py & 31, mz = pz & 31;
+                const int o = (mx >> 4) | ((my >> 4) << 1) | ((mz >> 4) << 2);
+                const uint32_t kk = dindex(cx, cy, cz, g.nd);
+                const uint32_t qq = (uint32_t)((mx & 15) + 16 * ((my & 15) + 16 * (mz & 15)));
+                const int off = across[e] ? (int)(((kk * 8u + (uint32_t)o) * 128u + (qq >> 5)) * 4u) : endA;
+                wv[e][i] = __builtin_amdgcn_raw_buffer_load_b32(A, off, 0, kCoherent);
+                bitp[e][i] = (int)(qq & 31u);
+                if (i == 0) {
+                    kj[e] = kk;
+                    oj[e] = o;
+                    slab[e] = across[e] ? (mz & 15) >> 2 : z >> 2;
+                }
+            }
+            // inside the octant: the class from LDS (a site inside stands in when across)
+            cls[e] = slab_class_lds(o, across[e] ? lx : x, across[e] ? ly : y, across[e] ? lz : z);
+        }
+        // every read consumed before the first count move goes out
+        int c_new[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const uint32_t sj = (wv[e][0] >> bitp[e][0]) & 1u;
+            int nup = (int)up;  // the flipped site, before its flip
+#pragma unroll
+            for (int i = 1; i < 6; ++i) nup += (int)((wv[e][i] >> bitp[e][i]) & 1u);
+            const int up_j = cls[e] >= 7;
+            const int nup_in = (up_j ? cls[e] - 7 : 6 - cls[e]);
+            cls[e] = across[e] ? site_class(sj, nup) : cls[e];
+            c_new[e] = across[e] ? site_class(sj, nup + dn) : site_class(up_j, nup_in + dn);
+        }
+        // (the classes pinned here: no count move may go out before both are known)
+        asm volatile("" ::"v"(cls[0]), "v"(cls[1]), "v"(c_new[0]), "v"(c_new[1]) : "memory");
+        // scatter: the class moves
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (across[e])
+                slab_move_dev(g.sc + ((uint64_t)kj[e] * 8 + (uint32_t)oj[e]) * kSlabWords, cls[e],
+                              c_new[e], slab[e]);
+            else
+                slab_move_lds(sc, cls[e], c_new[e], slab[e]);
         }
     }
 }
@@ -1962,7 +2060,7 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
                 const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
                 const int cs = row_class(sh.acc[ld], ld < nvalid, unit53(ux, uy) * Rspec, l, row);
                 cpred |= (uint32_t)(cs + 1) << (5 * pp);
-                slab_select(sh, ld, cs, uz, l, &sh.selq[ld], st);
+                slab_select(sh.sc[ld], sh.oct[ld], cs, uz, l, &sh.selq[ld], st);
             }
         }
         // the next cycle's draw (-ln u of its clock step, its colour), while the maxima travel
@@ -2023,7 +2121,7 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
                 const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
                 const int cs = row_class(sh.acc[ld], ld < nvalid, unit53(ux, uy) * Rmax, l, row);
                 if ((uint32_t)(cs + 1) != ((cpred >> (5 * pp)) & 31u))
-                    slab_select(sh, ld, cs, uz, l, &sh.selq[ld], st);
+                    slab_select(sh.sc[ld], sh.oct[ld], cs, uz, l, &sh.selq[ld], st);
             }
         }
         __syncthreads();
@@ -2037,95 +2135,8 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
             const uint32_t ld = (uint32_t)tid >> 2;
             const int part = tid & 3;
             const uint32_t f = ld < nvalid ? sh.selq[ld] : kNoEvent;
-            if (f != kNoEvent) {
-                const int cs = (int)(f >> 12);
-                const uint32_t q = f & 0xFFFu;
-                const int lx = (int)(q & 15u), ly = (int)((q >> 4) & 15u), lz = (int)(q >> 8);
-                const uint32_t up = cs >= 7;
-                const uint32_t k = kbase + ld;
-                if (part == 0) {
-                    slab_move_lds(sh.sc[ld], cs, site_class(!up, up ? cs - 7 : 6 - cs), lz >> 2);
-                    flip_site<16>(g, k, s, q);
-                    myF += 1;
-                    mydM += up ? -2 : 2;
-                    mydB += 12 - 4 * (long long)(cs % 7);
-                } else {
-                    // axis part - 1 as a unit vector, and the two axes across it
-                    const int ex = part == 1, ey = part == 2, ez = part == 3;
-                    const int ux1 = !ex, uy1 = ex;  // y for the x axis, else x
-                    const int uy2 = ez, uz2 = !ez;  // y for the z axis, else z
-                    const int dn = up ? -1 : 1;     // change of the neighbours' up counts
-                    const uint32_t dc = sh.dco[ld];
-                    const DomainCoord c = {(int)(dc & 1023u), (int)((dc >> 10) & 1023u), (int)(dc >> 20)};
-                    const int endA = (int)(g.N / 8u);
-                    const __amdgpu_buffer_rsrc_t A =
-                        __builtin_amdgcn_make_buffer_rsrc((void *)g.A, (short)0, endA, 0x00020000);
-                    // gather: a neighbour across a face reads its spin and its other five
-                    // neighbours from memory (none of them flips in this cycle), both
-                    // neighbours' reads in flight together; one inside the octant reads LDS
-                    uint32_t wv[2][6];
-                    int bitp[2][6], cls[2], slab[2];
-                    bool across[2];
-                    uint32_t kj[2];
-                    int oj[2];
-#pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const int side = e ? 1 : -1;
-                        const int x = lx + side * ex, y = ly + side * ey, z = lz + side * ez;
-                        const int along = ex ? x : ey ? y : z;
-                        across[e] = (unsigned)along > 15u;
-                        const int X = (s & 1) * 16 + x, Y = ((s >> 1) & 1) * 16 + y, Z = ((s >> 2) & 1) * 16 + z;
-                        const int PX[6] = {X, X + side * ex, X - ux1, X + ux1, X, X};
-                        const int PY[6] = {Y, Y + side * ey, Y - uy1, Y + uy1, Y - uy2, Y + uy2};
-                        const int PZ[6] = {Z, Z + side * ez, Z, Z, Z - uz2, Z + uz2};
-#pragma unroll
-                        for (int i = 0; i < 6; ++i) {
-                            const int px = PX[i], py = PY[i], pz = PZ[i];
-                            const int cx = px < 0 ? wrapm(c.kx, g.nd) : px >= 32 ? wrapp(c.kx, g.nd) : c.kx;
-                            const int cy = py < 0 ? wrapm(c.ky, g.nd) : py >= 32 ? wrapp(c.ky, g.nd) : c.ky;
-                            const int cz = pz < 0 ? wrapm(c.kz, g.nd) : pz >= 32 ? wrapp(c.kz, g.nd) : c.kz;
-                            const int mx = px & 31, my = py & 31, mz = pz & 31;
-                            const int o = (mx >> 4) | ((my >> 4) << 1) | ((mz >> 4) << 2);
-                            const uint32_t kk = dindex(cx, cy, cz, g.nd);
-                            const uint32_t qq = (uint32_t)((mx & 15) + 16 * ((my & 15) + 16 * (mz & 15)));
-                            const int off = across[e] ? (int)(((kk * 8u + (uint32_t)o) * 128u + (qq >> 5)) * 4u) : endA;
-                            wv[e][i] = __builtin_amdgcn_raw_buffer_load_b32(A, off, 0, kCoherent);
-                            bitp[e][i] = (int)(qq & 31u);
-                            if (i == 0) {
-                                kj[e] = kk;
-                                oj[e] = o;
-                                slab[e] = across[e] ? (mz & 15) >> 2 : z >> 2;
-                            }
-                        }
-                        // inside the octant: the class from LDS (a site inside stands in when across)
-                        cls[e] = slab_class_lds(sh.oct[ld], across[e] ? lx : x, across[e] ? ly : y, across[e] ? lz : z);
-                    }
-                    // every read consumed before the first count move goes out
-                    int c_new[2];
-#pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        const uint32_t sj = (wv[e][0] >> bitp[e][0]) & 1u;
-                        int nup = (int)up;  // the flipped site, before its flip
-#pragma unroll
-                        for (int i = 1; i < 6; ++i) nup += (int)((wv[e][i] >> bitp[e][i]) & 1u);
-                        const int up_j = cls[e] >= 7;
-                        const int nup_in = (up_j ? cls[e] - 7 : 6 - cls[e]);
-                        cls[e] = across[e] ? site_class(sj, nup) : cls[e];
-                        c_new[e] = across[e] ? site_class(sj, nup + dn) : site_class(up_j, nup_in + dn);
-                    }
-                    // (the classes pinned here: no count move may go out before both are known)
-                    asm volatile("" ::"v"(cls[0]), "v"(cls[1]), "v"(c_new[0]), "v"(c_new[1]) : "memory");
-                    // scatter: the class moves
-#pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        if (across[e])
-                            slab_move_dev(g.sc + ((uint64_t)kj[e] * 8 + (uint32_t)oj[e]) * kSlabWords, cls[e],
-                                          c_new[e], slab[e]);
-                        else
-                            slab_move_lds(sh.sc[ld], cls[e], c_new[e], slab[e]);
-                    }
-                }
-            }
+            if (f != kNoEvent)
+                slab_flip_part(g, sh.oct[ld], sh.sc[ld], sh.dco[ld], kbase + ld, s, f, part, myF, mydM, mydB);
         }
         // this thread's flips and count moves complete (the flag below publishes them)
         if (publish_flag) __builtin_amdgcn_s_waitcnt(0);
@@ -2254,6 +2265,197 @@ __global__ void __launch_bounds__(kSlabBlock) k_slab(Replica R) {
 }
 
 // ---------------------------------------------------------------------------
+// Per-cycle slab kernels (PACKED, octant edge 16, eight colours): one cycle in
+// two launches from the slab counts, for lattices of any size.  k_srows_max
+// takes every line's frequency line (every octant's with the all-octant R_max)
+// from its count words and the largest into st->rmax[0]; k_srows_select stages
+// each line's counts, octant and halo in LDS, draws, selects in one slab and
+// flips (the class moves as in the slab engine).  The counts are binned once per
+// run by k_slab_bin; kernel boundaries order every read after the writes it needs.
+// ---------------------------------------------------------------------------
+struct SrowsShared {
+    uint32_t oct[kSlabDomains][kOctLds];
+    uint32_t sc[kSlabDomains][kSlabWords];
+    double acc[kSlabDomains][14];
+    uint32_t nbdom[kSlabDomains][6];
+    uint32_t dco[kSlabDomains];
+    uint32_t selq[kSlabDomains];
+    uint32_t zbuf[kSlabRows][24];
+    unsigned long long wmax;
+    long long red[3][16];
+};
+
+// The slab counts of every octant of 128 domains per workgroup, from the spins.
+__global__ void __launch_bounds__(kSlabBlock) k_slab_bin(Geom g) {
+    __shared__ SrowsShared sh;
+    const int tid = threadIdx.x, row = tid >> 4, l = tid & 15;
+    const uint32_t kbase = blockIdx.x * kSlabDomains;
+    const uint32_t nvalid = kbase >= g.K ? 0u : (g.K - kbase < kSlabDomains ? g.K - kbase : kSlabDomains);
+    for (uint32_t i = tid; i < nvalid * 6; i += kSlabBlock) {
+        const uint32_t ldm = i / 6;
+        const int dir = (int)(i % 6), a = dir >> 1;
+        const DomainCoord c = dcoord(kbase + ldm, g.nd);
+        int kc[3] = {c.kx, c.ky, c.kz};
+        kc[a] = (dir & 1) ? wrapp(kc[a], g.nd) : wrapm(kc[a], g.nd);
+        sh.nbdom[ldm][dir] = dindex(kc[0], kc[1], kc[2], g.nd);
+    }
+    if (l < 8) sh.zbuf[row][16 + l] = 0;
+    __syncthreads();
+#pragma unroll 1
+    for (int o = 0; o < 8; ++o) slab_bin_octant(g, kbase, nvalid, o, sh);
+}
+
+// Every line's frequency line from its count words (with the all-octant R_max:
+// every octant of every domain), the largest into st->rmax[0].  One thread per
+// line (or octant).
+template <int LPD>
+__global__ void __launch_bounds__(256) k_srows_max(Geom g, uint64_t n) {
+    __shared__ unsigned long long wmax;
+    const int tid = threadIdx.x;
+    const bool all = (g.variant & SPKMC_VARIANT_RMAX_ALL) != 0;
+    const uint32_t lpd = LPD ? (uint32_t)LPD : g.lpd;
+    const uint64_t units = all ? (uint64_t)g.K * 8u : (uint64_t)g.K * lpd;
+    const uint64_t u = (uint64_t)blockIdx.x * 256u + (uint64_t)tid;
+    if (tid == 0) wmax = 0;
+    __syncthreads();
+    if (u < units) {
+        const int s = cycle_draw(g.seed, n, lpd == 4).colour;
+        uint32_t k, o;
+        if (all) {
+            k = (uint32_t)(u >> 3);
+            o = (uint32_t)(u & 7u);
+        } else {
+            k = lpd == 1 ? (uint32_t)u : (uint32_t)(u >> 2);
+            o = (uint32_t)(lpd == 1 ? s : two_colour_octant(s, (uint32_t)(u & 3u)));
+        }
+        const uint32_t *w = g.sc + ((uint64_t)k * 8u + o) * kSlabWords;
+        uint32_t cnt[14];
+#pragma unroll
+        for (int c = 0; c < 14; ++c) {
+            const uint32_t v0 = w[2 * c], v1 = w[2 * c + 1];
+            cnt[c] = (v0 & 0xFFFFu) + (v0 >> 16) + (v1 & 0xFFFFu) + (v1 >> 16);
+        }
+        atomicMax(&wmax, (unsigned long long)double_to_bits(line_total(cnt, g.r)));
+    }
+    __syncthreads();
+    if (tid == 0 && wmax) atomicMax((unsigned long long *)&g.st->rmax[0], wmax);
+}
+
+template <int LPD>
+__global__ void __launch_bounds__(kSlabBlock) k_srows_select(Geom g, uint64_t n) {
+    __shared__ SrowsShared sh;
+    using RG = RowsGeometry<16, kSlabBlock, LPD, kSlabPasses>;
+    constexpr int rows = RG::rows, P = RG::P;
+    constexpr uint32_t D = RG::D;
+    const RG rg(g);
+    const int tid = threadIdx.x, row = tid >> 4, l = tid & 15;
+    const int s = cycle_draw(g.seed, n, rg.lpd == 4).colour;
+    const double Rmax = (g.variant & SPKMC_VARIANT_RMAX_BOUND) ? g.rbound : bits_to_double(g.st->rmax[0]);
+    rg.neighbours(sh.nbdom);
+    for (uint32_t i = tid; i < rg.nvalid; i += kSlabBlock) {
+        const DomainCoord c = dcoord(rg.dom(rg.kbase + i), g.nd);
+        sh.dco[i] = (uint32_t)c.kx | ((uint32_t)c.ky << 10) | ((uint32_t)c.kz << 20);
+    }
+    __syncthreads();
+    // each line's counts (lane c: class c) and its octant and halo, into LDS
+    const int endSC = (int)((uint64_t)g.K * 8u * kSlabWords * 4u);
+    const __amdgpu_buffer_rsrc_t SC = __builtin_amdgcn_make_buffer_rsrc((void *)g.sc, (short)0, endSC, 0x00020000);
+#pragma unroll
+    for (int pp = 0; pp < P; ++pp) {
+        const uint32_t ld = (uint32_t)(pp * rows + row);
+        const bool valid = ld < rg.nvalid;
+        const uint32_t k = rg.dom(rg.kbase + ld), o = (uint32_t)rg.oct(rg.kbase + ld, s);
+        const int off = valid && l < 14 ? (int)(((k * 8u + o) * kSlabWords + 2u * (uint32_t)l) * 4u) : endSC;
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(SC, off, 0, kCoherent);
+        Raw<16> raw;
+        load_octant<16>(g, k, (int)o, valid, l, sh.nbdom[valid ? ld : 0], raw);
+        if (l < 14) {
+            sh.sc[ld][2 * l] = v[0];
+            sh.sc[ld][2 * l + 1] = v[1];
+        }
+        uint32_t *oc = sh.oct[ld];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) oc[8 * l + w] = raw.W[w];
+        if (!(l & 1)) {
+            oc[kFxm + (l >> 1)] = raw.xm;
+            oc[kFxp + (l >> 1)] = raw.xp;
+            oc[kFym + (l >> 1)] = raw.ym;
+            oc[kFyp + (l >> 1)] = raw.yp;
+        }
+        oc[kFzm + l] = raw.zw;
+    }
+    __syncthreads();
+    // running sums of every line, in the order of step 1
+    for (uint32_t i = tid; i < D; i += kSlabBlock) {
+        double a = 0.0;
+        for (int c = 0; c < 14; ++c) {
+            const uint32_t v0 = sh.sc[i][2 * c], v1 = sh.sc[i][2 * c + 1];
+            const uint32_t cnt = (v0 & 0xFFFFu) + (v0 >> 16) + (v1 & 0xFFFFu) + (v1 >> 16);
+            double term = (double)cnt * g.r[c];
+            a = a + term;
+            sh.acc[i][c] = a;
+        }
+    }
+    __syncthreads();
+    // lane pp of each row draws for the row's line of pass pp
+    U4 dw;
+    {
+        const uint32_t kd = rg.kbase + (uint32_t)((l < P ? l : 0) * rows + row);
+        dw = philox10((uint32_t)n, (uint32_t)(n >> 32), rg.dom(kd), (uint32_t)rg.oct(kd, s), g.seed);
+    }
+#pragma unroll
+    for (int pp = 0; pp < P; ++pp) {
+        const uint32_t ld = (uint32_t)(pp * rows + row);
+        const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
+        const int cs = row_class(sh.acc[ld], ld < rg.nvalid, unit53(ux, uy) * Rmax, l, row);
+        slab_select(sh.sc[ld], sh.oct[ld], cs, uz, l, &sh.selq[ld], g.st);
+    }
+    __syncthreads();
+    long long F = 0, dM = 0, dB = 0;
+    {
+        const uint32_t ld = (uint32_t)tid >> 2;
+        const int part = tid & 3;
+        const uint32_t f = ld < rg.nvalid ? sh.selq[ld] : kNoEvent;
+        if (f != kNoEvent)
+            slab_flip_part(g, sh.oct[ld], sh.sc[ld], sh.dco[ld], rg.dom(rg.kbase + ld), rg.oct(rg.kbase + ld, s), f,
+                           part, F, dM, dB);
+    }
+    __syncthreads();
+    // the lines' counts back to memory (lane c of a row: class c)
+#pragma unroll
+    for (int pp = 0; pp < P; ++pp) {
+        const uint32_t ld = (uint32_t)(pp * rows + row);
+        if (ld < rg.nvalid && l < 14) {
+            const uint32_t k = rg.dom(rg.kbase + ld), o = (uint32_t)rg.oct(rg.kbase + ld, s);
+            *reinterpret_cast<uint64_t *>(g.sc + ((uint64_t)k * 8u + o) * kSlabWords + 2 * l) =
+                (uint64_t)sh.sc[ld][2 * l] | ((uint64_t)sh.sc[ld][2 * l + 1] << 32);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        F += __shfl_xor(F, o);
+        dM += __shfl_xor(dM, o);
+        dB += __shfl_xor(dB, o);
+    }
+    if ((tid & 63) == 0) {
+        sh.red[0][tid >> 6] = F;
+        sh.red[1][tid >> 6] = dM;
+        sh.red[2][tid >> 6] = dB;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        F = dM = dB = 0;
+        for (int w = 0; w < kSlabBlock / 64; ++w) {
+            F += sh.red[0][w];
+            dM += sh.red[1][w];
+            dB += sh.red[2][w];
+        }
+        if (F) atomicAdd((unsigned long long *)&g.st->acc_fired[0], (unsigned long long)F);
+        if (dM) atomicAdd((unsigned long long *)&g.st->acc_dM[0], (unsigned long long)dM);
+        if (dB) atomicAdd((unsigned long long *)&g.st->acc_dB[0], (unsigned long long)dB);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 // Launch shapes.  A 16-lane row owns a domain; a workgroup runs `rows` rows
@@ -2353,6 +2555,33 @@ static hipError_t launch_rows(const Geom &g, uint64_t n, hipStream_t stream) {
         hipLaunchKernelGGL((k_rows_bin<H, BLOCK, 1, P>), dim3(grid), dim3(BLOCK), 0, stream, g, n);
         hipLaunchKernelGGL((k_rows_select<H, BLOCK, 1, P>), dim3(grid), dim3(BLOCK), 0, stream, g, n);
     }
+    return hipGetLastError();
+}
+
+// Eight colours only: with two colours a neighbour across a face of a flipped
+// site can have, diagonally, a site of another active octant that flips in the
+// same cycle, and the two flips' class moves of that neighbour would each start
+// from a stale class.  With eight colours that diagonal octant is never active.
+bool slab_rows_supported(const Geom &g) {
+    return g.layout == SPKMC_LAYOUT_PACKED && g.h == 16 && g.lpd == 1 && g.sc && g.N / 8 < (1ull << 31);
+}
+
+hipError_t launch_slab_bin(const Geom &g, hipStream_t stream) {
+    if (!slab_rows_supported(g)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_slab_bin, dim3((g.K + kSlabDomains - 1) / kSlabDomains), dim3(kSlabBlock), 0, stream, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_cycle_slab(const Geom &g, uint64_t n, hipStream_t stream) {
+    if (!slab_rows_supported(g)) return hipErrorInvalidValue;
+    const uint64_t lines = (uint64_t)g.K * g.lpd;
+    const uint32_t grid = (uint32_t)((lines + kSlabDomains - 1) / kSlabDomains);
+    if (!(g.variant & SPKMC_VARIANT_RMAX_BOUND)) {
+        const uint64_t units = (g.variant & SPKMC_VARIANT_RMAX_ALL) ? (uint64_t)g.K * 8u : lines;
+        const uint32_t mgrid = (uint32_t)((units + 255) / 256);
+        hipLaunchKernelGGL(k_srows_max<1>, dim3(mgrid), dim3(256), 0, stream, g, n);
+    }
+    hipLaunchKernelGGL(k_srows_select<1>, dim3(grid), dim3(kSlabBlock), 0, stream, g, n);
     return hipGetLastError();
 }
 

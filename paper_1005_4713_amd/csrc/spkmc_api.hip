@@ -284,8 +284,12 @@ spkmc_status spkmc_run(spkmc_ctx *c, uint64_t ncycles, uint32_t obs_every) {
         if (e != hipSuccess) return hip_fail(c, e, "persistent kernel launch");
         c->cycle += ncycles;
     } else {
+        // PACKED lattices with octant edge 16 run the slab kernels, whose counts
+        // are binned afresh at the start of every run
+        const bool slab = slab_rows_supported(c->g);
+        if (slab && (e = launch_slab_bin(c->g, c->stream)) != hipSuccess) return hip_fail(c, e, "slab count kernel");
         for (uint64_t i = 0; i < ncycles; ++i) {
-            e = launch_cycle(c->g, c->cycle, obs_every, c->stream);
+            e = launch_cycle(c->g, c->cycle, obs_every, c->stream, slab);
             if (e != hipSuccess) return hip_fail(c, e, "cycle kernel launch");
             c->cycle += 1;
         }
