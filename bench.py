@@ -151,6 +151,19 @@ def cpu_baseline(w, cycles):
             "attempts_per_s": (st1[1] + st1[2] - st0[1] - st0[2]) / dt}
 
 
+def serial_bkl_baseline(events=2_500_000):
+    """The oracle's serial rejection-free (BKL) simulator, single-threaded, at
+    L = 128, T_c: the classic serial method, for reference beside the oracle's
+    spkMC (a bounded number of events from a random start)."""
+    import oracle
+    b = oracle.Bkl(L=128, d=8, J=1.0, H=0.0, T=4.5115, seed=2)
+    t0 = time.perf_counter()
+    b.run(events)
+    dt = time.perf_counter() - t0
+    return {"value": events / dt, "unit": "spin-flip events/s", "cores": 1, "kind": "oracle serial BKL",
+            "sample": f"{events} events of L=128, T=4.5115 from a random start in {dt:.2f} s"}
+
+
 def _serve_run(spkmc, specs, doms, arrivals, pool_bytes, macro, max_live, log):
     """Submit request i at arrivals[i] seconds (real time) and step the server
     until every request is done; returns per-request latencies and totals."""
@@ -493,12 +506,17 @@ def main():
                      "bytes_per_cycle": bytes_cycle, "launches": launches,
                      "avg_launch_ms": gpu_ms / launches,
                      "traffic_source": None if traffic is None else traffic_rec["path"],
-                     "valu": measured_valu(w["name"], kernel) if launches == 1 and not args.variant else None},
+                     "valu": measured_valu(w["name"], kernel) if launches == 1 and not args.variant else None,
+                     # the lower bound of the bytes a cycle must move: the active octants'
+                     # own bits only (class masks without a halo), K h^3 / 8
+                     "frac_lower_bound_bytes": (info["K"] * info["h"] ** 3 / 8.0) * args.steps / secs / 1e9
+                     / HBM_PEAK_GBS},
     }
     if not args.no_cpu_baseline:
         cyc = args.cpu_cycles or (12 if w["L"] >= 1024 else 80 if w["L"] >= 512 else 4000)
         print(f"bench: cpu baseline, {cyc} oracle cycles", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, cyc)
+        out["cpu_baseline"]["serial_bkl"] = serial_bkl_baseline()
     print(json.dumps(out), flush=True)
 
 
