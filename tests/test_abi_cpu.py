@@ -189,3 +189,17 @@ def test_two_colours_sizes_four_lines_per_domain(spkmc):
     two = spkmc.state_bytes(spkmc.make_params(64, 16, variant="two_colours"))
     K = (64 // 16) ** 3
     assert two - one >= 3 * K * (8 + 64) - 512  # R_k and histogram of three more lines per domain
+
+
+def test_batch_calls_reject_bad_arguments(spkmc):
+    """Batch and batch-graph calls check their arguments before any device call."""
+    g = C.c_void_p()
+    cyc = (C.c_uint64 * 1)(10)
+    ws = C.c_void_p(0)
+    assert spkmc.lib.spkmc_run_batch(None, 0, cyc, 0, 0, ws, 0, None) == spkmc.E_INVAL
+    assert spkmc.lib.spkmc_batch_graph_create(None, 0, cyc, 0, 0, ws, 0, None, C.byref(g)) == spkmc.E_INVAL
+    assert not g.value
+    ctxs = (C.c_void_p * 1)(None)
+    assert spkmc.lib.spkmc_batch_graph_create(ctxs, 1, cyc, 0, 0, ws, 0, None, None) == spkmc.E_INVAL
+    assert spkmc.lib.spkmc_batch_graph_launch(None, 1) == spkmc.E_INVAL
+    spkmc.lib.spkmc_batch_graph_destroy(None)
