@@ -268,7 +268,8 @@ class Sim(_Lattice):
         self.N = self.L ** 3
 
     def _free(self):
-        if getattr(self, "ctx", None) and self.ctx.value:
+        # (at interpreter exit the module's globals may already be gone)
+        if getattr(self, "ctx", None) and self.ctx.value and lib is not None:
             lib.spkmc_destroy(self.ctx)
             self.ctx = C.c_void_p()
 
@@ -379,7 +380,7 @@ class Server:
             raise SpkmcError(st, lib.spkmc_server_last_error(self.h).decode())
 
     def close(self):
-        if getattr(self, "h", None) and self.h.value:
+        if getattr(self, "h", None) and self.h.value and lib is not None:
             lib.spkmc_server_destroy(self.h)
             self.h = C.c_void_p()
 
