@@ -235,7 +235,8 @@ size_t spkmc_batch_workspace_bytes(size_t n);
  * own clock, R_max, random streams and records, and the result of every
  * lattice is bit-identical to running it alone with spkmc_run.  All contexts
  * must use the PACKED layout with the same octant edge (8 or 16) and the same
- * stream, and the launch must fit on the device at once (E_UNSUPPORTED
+ * stream, each context at most once (E_INVAL otherwise; a context with
+ * ncycles 0 is not counted), and the launch must fit on the device at once (E_UNSUPPORTED
  * otherwise: split the batch).  wg_domains: domains per workgroup (0 = the
  * fewest passes that fit).  dev_workspace: spkmc_batch_workspace_bytes(n)
  * bytes of device memory owned by the caller; it must stay untouched until
@@ -252,7 +253,9 @@ spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *n
  * must stay untouched until the graph is destroyed and its last replay has
  * finished.  Nothing runs at creation but the descriptor upload.  While the
  * graph lives its members advance only through spkmc_batch_graph_launch
- * (E_STATE from there if a member's cycle count moved otherwise).  Replays are
+ * (E_STATE from there if a member's cycle count moved otherwise), and every
+ * member context must outlive the graph (the graph keeps pointers to them;
+ * destroying a member first leaves them dangling).  Replays are
  * bit-identical to spkmc_run_batch and to solo runs.  The batch kernel is a
  * cooperative graph node.  E_UNSUPPORTED if the runtime cannot build or
  * instantiate the graph. */

@@ -3,6 +3,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -534,6 +535,8 @@ static spkmc_status plan_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t 
         if (!c) return fail(nullptr, SPKMC_E_INVAL, "NULL context in batch");
         if (c->failed || !c->dev) return fail(nullptr, SPKMC_E_STATE, "a context of the batch is in a failed state");
         if (ncycles[i] == 0) continue;
+        if (std::find(bp.live.begin(), bp.live.end(), c) != bp.live.end())
+            return fail(nullptr, SPKMC_E_INVAL, "a context appears twice in the batch");
         std::string why;
         if (!persistent_supported(c->g, c->p, false, why)) return fail(nullptr, SPKMC_E_UNSUPPORTED, "batch member: " + why);
         if (bp.live.empty()) {

@@ -92,3 +92,23 @@ def test_batch_rejects_mixed_edges(spkmc):
     a.run(5)
     b.run(5)
     assert a.state()[0] == 5 and b.state()[0] == 5
+
+
+def test_batch_rejects_a_context_twice(spkmc):
+    """A lattice listed twice would run as two replicas over one state: refused
+    before any launch; listed again with 0 cycles it is not a member and runs once."""
+    print("case batch duplicate", flush=True)
+    a = spkmc.Sim(64, 16, layout="packed", seed=3)
+    b = spkmc.Sim(64, 16, layout="packed", seed=4)
+    ref = spkmc.Sim(64, 16, layout="packed", seed=3)
+    with pytest.raises(spkmc.SpkmcError) as ei:
+        spkmc.run_batch([a, b, a], 10)
+    assert ei.value.status == spkmc.E_INVAL
+    with pytest.raises(spkmc.SpkmcError) as ei:
+        spkmc.BatchGraph([a, a], 10)
+    assert ei.value.status == spkmc.E_INVAL
+    assert a.state()[0] == 0 and b.state()[0] == 0
+    spkmc.run_batch([a, b, a], [10, 10, 0])
+    ref.run(10)
+    assert a.state() == ref.state()
+    assert np.array_equal(a.spins(), ref.spins())
