@@ -80,7 +80,8 @@ enum { SPKMC_INIT_RANDOM = 0, SPKMC_INIT_UP = 1, SPKMC_INIT_DOWN = 2 };
 enum { SPKMC_LAYOUT_INT8 = 0, SPKMC_LAYOUT_PACKED = 1 };
 /* Kernel engine.  AUTO picks PERSISTENT when supported (and when the domains
  * fit in one resident launch), else CYCLE.
- * CYCLE: three launches per cycle (bin, select-and-flip, finalize), any layout.
+ * CYCLE: three launches per cycle (bin, select-and-flip, finalize), any layout
+ * and size (the only engine for lattices of 2^34 sites or more).
  * PERSISTENT: one cooperative launch per spkmc_run call with a device-wide R_max
  * exchange every cycle (PACKED layout, h = 8 or 16); every cycle bins the
  * active octant of every domain afresh.
@@ -173,10 +174,11 @@ size_t spkmc_state_bytes(const spkmc_params *p);
  * enqueue the initial state on `hip_stream` (a hipStream_t; NULL = null stream).
  * *out receives the context (also on some errors, so spkmc_last_error can be
  * read; destroy it either way).
- * Errors: E_INVAL (bad parameters: d odd, d < 2, L % d != 0, T <= 0, a rate
- * that is 0 or not finite, unknown enum, wrong struct_size, unknown variant
- * bits or RMAX_ALL with RMAX_BOUND,
- * PACKED with h % 4 != 0), E_RANGE (dev_bytes too small), E_UNSUPPORTED
+ * Errors: E_INVAL (bad parameters: d odd, d < 2, L % d != 0, L > 4096, T <= 0,
+ * a rate that is 0 or not finite, unknown enum, wrong struct_size, unknown
+ * variant bits or RMAX_ALL with RMAX_BOUND, PACKED with h % 4 != 0, 2^31 or
+ * more frequency lines: (L/d)^3 domains, times 4 with TWO_COLOURS), E_RANGE
+ * (dev_bytes too small), E_UNSUPPORTED
  * (engine PERSISTENT with parameters it cannot run), E_DEVICE. */
 spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, void *hip_stream,
                         spkmc_ctx **out);

@@ -117,6 +117,7 @@ __global__ void k_observables(Geom g) {
 }
 
 // --------------------------------------------------------------------------- cycle
+constexpr unsigned kCycleMaxGrid = 1u << 20;  // workgroups of one generic per-cycle launch
 // Frequency line f of a cycle: domain f / lpd, octant = the colour (eight
 // colours) or the (f mod 4)-th octant of the colour's parity (two colours).
 __device__ __forceinline__ void line_of(const Geom &g, uint32_t f, int colour, uint32_t &k, int &s) {
@@ -141,60 +142,67 @@ __device__ __forceinline__ void bin_octant(const Geom &g, uint32_t k, int s, uin
     }
 }
 
-// Step 1 and the device-wide max of step 2.  One workgroup per frequency line.
-// RMAX_ALL: the workgroup also bins the inactive octants it stands for (the
-// other seven with eight colours, octant s ^ 1 with two) into the maximum;
-// RMAX_BOUND: no maximum is taken.
+// Step 1 and the device-wide max of step 2.  One workgroup per frequency line
+// (lines f = blockIdx.x, blockIdx.x + gridDim.x, ... when the lines outnumber the
+// grid).  RMAX_ALL: the workgroup also bins the inactive octants each line
+// stands for (the other seven with eight colours, octant s ^ 1 with two) into
+// the maximum; RMAX_BOUND: no maximum is taken.
 template <class S>
 __global__ void k_bin(Geom g, uint64_t n) {
     __shared__ uint32_t cnt[16];
-    const uint32_t f = blockIdx.x;
+    const uint32_t lines = g.K * g.lpd;  // < 2^31 (checked at set-up)
     const bool two = g.lpd == 4;
-    CycleDraw cd = cycle_draw(g.seed, n, two);
-    uint32_t k;
-    int s;
-    line_of(g, f, cd.colour, k, s);
-    if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    bin_octant<S>(g, k, s, cnt);
-    __syncthreads();
-    double Rk = 0.0;
-    if (threadIdx.x == 0) {
-        Rk = line_total(cnt, g.r);
-        g.Rk[f] = Rk;
-        for (int c = 0; c < 16; ++c) g.hist[(uint64_t)f * 16 + c] = c < 14 ? cnt[c] : 0;
-    }
-    if (g.variant & SPKMC_VARIANT_RMAX_BOUND) return;
-    if (g.variant & SPKMC_VARIANT_RMAX_ALL) {
-        for (int o = 0; o < 8; ++o) {
-            if (o == s || (two && o != (s ^ 1))) continue;
-            __syncthreads();
-            if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
-            __syncthreads();
-            bin_octant<S>(g, k, o, cnt);
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double Ro = line_total(cnt, g.r);
-                if (Ro > Rk) Rk = Ro;
+    const CycleDraw cd = cycle_draw(g.seed, n, two);
+    double wmax = 0.0;  // thread 0: the largest line of this workgroup
+    for (uint32_t f = blockIdx.x; f < lines; f += gridDim.x) {
+        uint32_t k;
+        int s;
+        line_of(g, f, cd.colour, k, s);
+        __syncthreads();  // the previous line's counts are read
+        if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        bin_octant<S>(g, k, s, cnt);
+        __syncthreads();
+        double Rk = 0.0;
+        if (threadIdx.x == 0) {
+            Rk = line_total(cnt, g.r);
+            g.Rk[f] = Rk;
+            for (int c = 0; c < 16; ++c) g.hist[(uint64_t)f * 16 + c] = c < 14 ? cnt[c] : 0;
+        }
+        if (g.variant & SPKMC_VARIANT_RMAX_ALL) {
+            for (int o = 0; o < 8; ++o) {
+                if (o == s || (two && o != (s ^ 1))) continue;
+                __syncthreads();
+                if (threadIdx.x < 16) cnt[threadIdx.x] = 0;
+                __syncthreads();
+                bin_octant<S>(g, k, o, cnt);
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double Ro = line_total(cnt, g.r);
+                    if (Ro > Rk) Rk = Ro;
+                }
             }
         }
+        if (Rk > wmax) wmax = Rk;
     }
-    if (threadIdx.x == 0) atomicMax((unsigned long long *)&g.st->rmax[0], (unsigned long long)double_to_bits(Rk));
+    if (threadIdx.x == 0 && !(g.variant & SPKMC_VARIANT_RMAX_BOUND) && blockIdx.x < lines)
+        atomicMax((unsigned long long *)&g.st->rmax[0], (unsigned long long)double_to_bits(wmax));
 }
 
-// Steps 3, 4, 4b and the flip.  One 64-lane wavefront per domain, four per workgroup.
+// Steps 3, 4, 4b and the flip.  One 64-lane wavefront per frequency line, four
+// per workgroup (lines f, f + 4 gridDim.x, ... when the lines outnumber the grid).
 template <class S>
 __global__ void __launch_bounds__(256) k_select(Geom g, uint64_t n) {
     __shared__ long long part[4][3];
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint32_t f = blockIdx.x * 4 + wave;  // frequency line
+    const uint32_t lines = g.K * g.lpd;  // < 2^31 (checked at set-up)
+    const CycleDraw cd = cycle_draw(g.seed, n, g.lpd == 4);
+    const double Rmax = (g.variant & SPKMC_VARIANT_RMAX_BOUND) ? g.rbound : bits_to_double(g.st->rmax[0]);
     long long fired = 0, dM = 0, dB = 0;
-    if (f < g.K * g.lpd) {
-        CycleDraw cd = cycle_draw(g.seed, n, g.lpd == 4);
+    for (uint32_t f = blockIdx.x * 4 + wave; f < lines; f += gridDim.x * 4) {
         uint32_t k;
         int so;
         line_of(g, f, cd.colour, k, so);
-        double Rmax = (g.variant & SPKMC_VARIANT_RMAX_BOUND) ? g.rbound : bits_to_double(g.st->rmax[0]);
         U4 dw = philox10((uint32_t)n, (uint32_t)(n >> 32), k, (uint32_t)so, g.seed);
         double target = unit53(dw.x, dw.y) * Rmax;
         uint32_t cnt[14];
@@ -235,12 +243,12 @@ __global__ void __launch_bounds__(256) k_select(Geom g, uint64_t n) {
                                                 ly == e ? 3 * g.h2 + lx + g.h * lz : ~0u,
                                                 lz == 0 ? 4 * g.h2 + lx + g.h * ly : ~0u,
                                                 lz == e ? 5 * g.h2 + lx + g.h * ly : ~0u};
-                            for (int f = 0; f < 6; ++f)
-                                if (fidx[f] != ~0u) atomicXor(&F[fidx[f] >> 5], 1u << (fidx[f] & 31));
+                            for (int fc = 0; fc < 6; ++fc)
+                                if (fidx[fc] != ~0u) atomicXor(&F[fidx[fc] >> 5], 1u << (fidx[fc] & 31));
                         }
-                        fired = 1;
-                        dM = -2 * s;
-                        dB = 12 - 4 * a;
+                        fired += 1;
+                        dM += -2 * s;
+                        dB += 12 - 4 * a;
                     }
                     break;
                 }
@@ -248,7 +256,7 @@ __global__ void __launch_bounds__(256) k_select(Geom g, uint64_t n) {
             }
         }
     }
-    // wavefront sums of the one lane that flipped
+    // wavefront sums of the lanes that flipped
     for (int o = 32; o > 0; o >>= 1) {
         fired += __shfl_xor(fired, o);
         dM += __shfl_xor(dM, o);
@@ -323,14 +331,17 @@ hipError_t launch_cycle(const Geom &g, uint64_t n, uint32_t obs_every, hipStream
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, stream, g, n, obs_every);
         return hipGetLastError();
     }
-    unsigned bin_block = g.h3 >= 256 ? 256 : 64;
+    // grids capped well below the 2^32 work-items of one dispatch; the kernels
+    // stride over the remaining lines
+    const unsigned bin_block = g.h3 >= 256 ? 256 : 64;
     const unsigned lines = g.K * g.lpd;
-    unsigned sel_blocks = (lines + 3) / 4;
+    const unsigned bin_blocks = lines < kCycleMaxGrid ? lines : kCycleMaxGrid;
+    const unsigned sel_blocks = (lines + 3) / 4 < kCycleMaxGrid ? (lines + 3) / 4 : kCycleMaxGrid;
     if (g.layout == SPKMC_LAYOUT_INT8) {
-        hipLaunchKernelGGL(k_bin<Int8Spins>, dim3(lines), dim3(bin_block), 0, stream, g, n);
+        hipLaunchKernelGGL(k_bin<Int8Spins>, dim3(bin_blocks), dim3(bin_block), 0, stream, g, n);
         hipLaunchKernelGGL(k_select<Int8Spins>, dim3(sel_blocks), dim3(256), 0, stream, g, n);
     } else {
-        hipLaunchKernelGGL(k_bin<PackedSpins>, dim3(lines), dim3(bin_block), 0, stream, g, n);
+        hipLaunchKernelGGL(k_bin<PackedSpins>, dim3(bin_blocks), dim3(bin_block), 0, stream, g, n);
         hipLaunchKernelGGL(k_select<PackedSpins>, dim3(sel_blocks), dim3(256), 0, stream, g, n);
     }
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, stream, g, n, obs_every);

@@ -69,6 +69,14 @@ static bool validate(const spkmc_params *p, std::string &why) {
     if (p->domain < 2 || (p->domain & 1)) { why = "domain edge must be even and >= 2"; return false; }
     if (p->L % p->domain) { why = "L must be a multiple of the domain edge"; return false; }
     if (p->L > 4096) { why = "L above 4096 is not supported"; return false; }
+    {
+        const uint64_t nd = (uint64_t)(p->L / p->domain);
+        const uint64_t lines = nd * nd * nd * ((p->variant & SPKMC_VARIANT_TWO_COLOURS) ? 4 : 1);
+        if (lines >= (1ull << 31)) {
+            why = "more than 2^31 - 1 frequency lines (domains times lines per domain): use larger domains";
+            return false;
+        }
+    }
     if (p->rates != SPKMC_RATES_GLAUBER && p->rates != SPKMC_RATES_METROPOLIS) { why = "unknown rates"; return false; }
     if (p->init < 0 || p->init > 2) { why = "unknown init"; return false; }
     if (p->layout != SPKMC_LAYOUT_INT8 && p->layout != SPKMC_LAYOUT_PACKED) { why = "unknown layout"; return false; }

@@ -49,7 +49,10 @@ def test_struct_sizes_match_header(spkmc):
                                 dict(L=16, domain=8, T=0.0), dict(L=16, domain=8, T=-1.0),
                                 dict(L=16, domain=8, T=1e-3), dict(L=12, domain=6, layout="packed"),
                                 dict(L=16, domain=4, layout="packed"), dict(L=16, domain=8, rates=7),
-                                dict(L=16, domain=8, init=5), dict(L=16, domain=8, engine=9)])
+                                dict(L=16, domain=8, init=5), dict(L=16, domain=8, engine=9),
+                                dict(L=8192, domain=32, layout="packed"),       # L above 4096
+                                dict(L=4096, domain=2),                         # 2^33 lines
+                                dict(L=2048, domain=2, variant=2)])             # 2^32 lines (two colours)
 def test_invalid_parameters(spkmc, kw):
     p = spkmc.make_params(**kw)
     assert spkmc.state_bytes(p) == 0

@@ -151,3 +151,20 @@ def test_errors_do_not_abort(spkmc):
         s.load(b"x" * 10)
     s.run(10)
     assert s.state()[0] == 10
+
+
+@pytest.mark.parametrize("L,d,variant", [(512, 2, 0), (256, 2, 2)])
+def test_lines_beyond_one_grid(spkmc, L, d, variant):
+    """More frequency lines than one generic per-cycle launch has workgroups
+    (2^20): L = 512, d = 2 gives 2^24 lines (16 per bin workgroup, 4 per select
+    wavefront); L = 256, d = 2 with two colours gives 2^23.  Two cycles against
+    the oracle with a record each, every spin compared."""
+    _print_case(L=L, d=d, variant=variant)
+    gpu = spkmc.Sim(L, d, layout="int8", T=4.5115, seed=13, variant=variant, record_cap=16)
+    assert gpu.info()["engine"] == spkmc.ENGINES["cycle"]
+    orc = oracle.Sim(L=L, d=d, T=4.5115, seed=13, colours=2 if variant & 2 else 8)
+    gpu.run(2, obs_every=1)
+    recs_o = orc.run(2, obs_every=1)
+    for g, o in zip(gpu.records(2), recs_o):
+        _same_record(g, o)
+    assert np.array_equal(gpu.spins(), orc.spins())
