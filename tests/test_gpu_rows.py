@@ -92,3 +92,26 @@ def test_headline_size_engines_agree(spkmc):
     M = int(s.sum(dtype=np.int64))
     B = sum(int((s * np.roll(s, 1, ax)).sum(dtype=np.int64)) for ax in range(3))
     assert (sa[4], sa[5]) == (M, B)
+
+
+def test_largest_power_of_two_lattice(spkmc):
+    """L = 2048 (2^33 sites: 1 GiB packed, 8 GiB as int8), d = 32, T_c: the
+    per-cycle slab kernels (packed, word offsets up to 2^28) and the generic
+    kernels (int8) agree record for record over four cycles, and every cycle
+    accounts for each of the 2^18 domains once (an event or a null)."""
+    import torch
+    L, d, cycles = 2048, 32, 4
+    print("case L2048 packed vs int8", flush=True)
+    runs = []
+    for layout in ("packed", "int8"):
+        sim = spkmc.Sim(L, d, layout=layout, T=4.5115, seed=5, record_cap=8)
+        assert sim.info()["engine"] == spkmc.ENGINES["cycle"]
+        sim.run(cycles, obs_every=1)
+        runs.append((sim.state(), sim.records()))
+        del sim
+        torch.cuda.empty_cache()
+    (sa, ra), (sb, rb) = runs
+    assert sa == sb and ra == rb and len(ra) == cycles
+    K = (L // d) ** 3
+    for i, r in enumerate(ra):
+        assert r[0] == i + 1 and r[1] + r[2] == (i + 1) * K
