@@ -84,7 +84,10 @@ enum { SPKMC_LAYOUT_INT8 = 0, SPKMC_LAYOUT_PACKED = 1 };
  * and size (the only engine for lattices of 2^34 sites or more).
  * PERSISTENT: one cooperative launch per spkmc_run call with a device-wide R_max
  * exchange every cycle (PACKED layout, h = 8 or 16); every cycle bins the
- * active octant of every domain afresh.
+ * active octant of every domain afresh.  With h = 16 and more lines than one
+ * round of passes holds (up to 131 072 lines, e.g. two colours at L = 1024), the
+ * wide mode keeps only each line's moments from the bin and derives the class
+ * planes again for the selection, once the true R_max is known.
  * INCREMENTAL: the persistent launch, but the class histograms of all octants
  * stay on chip and follow every flip (the flipped site and its six neighbours
  * change class); a cycle classifies its active octant only to locate the
@@ -129,8 +132,12 @@ typedef struct spkmc_params {
     int32_t init;         /* SPKMC_INIT_*                                              */
     int32_t layout;       /* SPKMC_LAYOUT_*                                            */
     int32_t engine;       /* SPKMC_ENGINE_*                                            */
-    int32_t wg_domains;   /* PERSISTENT: domains per workgroup, 0 = default; other
-                             values change the launch shape, never the results      */
+    int32_t wg_domains;   /* PERSISTENT: frequency lines per workgroup, 0 = default
+                             (the fewest that fit the device at once); the row count
+                             (32 for octant edge 16, 64 for 8) times 1, 2 or 4 passes,
+                             for edge 16 also times 8 or 16 (the wide mode: two or
+                             four rounds of four passes).  Other values change the
+                             launch shape, never the results                        */
     uint32_t record_cap;  /* observation records kept on the device (ring)             */
     uint32_t variant;     /* SPKMC_VARIANT_* bits; 0 = 8 colours, R_max over the K
                              active octants                                          */

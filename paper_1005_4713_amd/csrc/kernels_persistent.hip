@@ -52,17 +52,19 @@
 
 namespace spkmc {
 
-// Workgroup-shared state of the persistent kernel.
-struct PersistShared {
-    double r[14];                      // rate table
-    uint32_t mom[kMaxWgDomains][13];   // per domain: the 13 popcount moments of its active octant
-    uint32_t hist[kMaxWgDomains][14];  // per domain: class histogram (re-binning engine)
-    uint32_t histp[kMaxWgDomains][8][7];  // per domain and octant: packed class counts (incremental engine)
-    double acc[kMaxWgDomains][14];     // per domain: running FP64 sums of the frequency line
-    double rk[kMaxWgDomains];
-    uint32_t zbuf[64][24];             // per row: z face words below (8), above (8), zeros (8)
-    uint32_t nbdom[kMaxWgDomains][6];  // per domain: the neighbour domains -x, +x, -y, +y, -z, +z
-    uint32_t selq[kMaxWgDomains];      // per row: (class << 12) | site q of its event, or kNoEvent
+// Workgroup-shared state of the persistent kernel for up to DMAX frequency lines
+// (HISTP: with the incremental engine's packed counts of all eight octants).
+template <uint32_t DMAX, bool HISTP>
+struct PersistSharedT {
+    double r[14];               // rate table
+    uint32_t mom[DMAX][13];     // per line: the 13 popcount moments of its active octant
+    uint32_t hist[DMAX][14];    // per line: class histogram (re-binning engine)
+    uint32_t histp[HISTP ? DMAX : 1][8][7];  // per domain and octant: packed class counts (incremental engine)
+    double acc[DMAX][14];       // per line: running FP64 sums of the frequency line
+    double rk[DMAX];
+    uint32_t zbuf[64][24];      // per row: z face words below (8), above (8), zeros (8)
+    uint32_t nbdom[DMAX][6];    // per line: its domain's neighbour domains -x, +x, -y, +y, -z, +z
+    uint32_t selq[DMAX];        // per line: (class << 12) | site q of its event, or kNoEvent
     double rpred[8];                   // per colour: the last R_max seen (the prediction)
     double rmax;
     int abort;
@@ -76,6 +78,12 @@ struct PersistShared {
     double pend_t[kRecBanks];
     uint32_t pend_bank[kRecBanks];
 };
+using PersistShared = PersistSharedT<kMaxWgDomains, true>;
+// The wide mode (octant edge 16): RND = 2 or 4 rounds of four passes of 32 rows,
+// 256 or 512 lines per workgroup.
+template <int RND>
+using PersistSharedWide = PersistSharedT<32 * 4 * RND, false>;
+static_assert(sizeof(PersistSharedWide<4>) <= 160 * 1024, "wide-mode LDS exceeds a CU's 160 KB");
 
 // Bin octant o of every domain of the workgroup (the 13 moments of each row, then
 // its histogram) into the packed counts of that octant.
@@ -117,8 +125,17 @@ __device__ __forceinline__ void bin_all(const Geom &g, uint32_t kbase, uint32_t 
 // neighbours change class, step 6); the active octant is classified only to
 // find the selected site, while the R_max exchange is in flight.
 // INC = false: the active octant of every domain is binned afresh each cycle.
-template <int H, int P, int BLOCK, bool INC, int LPD>
-__device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t gid, PersistShared &sh) {
+// Lane j (0..15) of this thread's 16-lane row, for a j known only at run time.
+__device__ __forceinline__ uint32_t row_lane(uint32_t v, int j) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(((threadIdx.x & 48u) + (uint32_t)j) << 2), (int)v);
+}
+
+// RND > 1 (the wide mode, re-binning engine only): each row runs RND rounds of P
+// lines; the bin keeps only their moments, the selection waits for the true
+// R_max and derives every round's class planes again from the spins.
+template <int H, int P, int BLOCK, bool INC, int LPD, int RND = 1, class SH = PersistShared>
+__device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t gid, SH &sh) {
+    static_assert(RND == 1 || (!INC && P * RND <= 16), "the wide mode re-bins; a row's lanes draw for its lines");
     const Geom &g = R.g;
     const PersistScratch &xs = R.xs;
     const uint64_t n0 = R.n0, ncycles = R.ncycles;
@@ -128,7 +145,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     const int tid = threadIdx.x;
     const int row = tid >> 4, l = tid & 15;  // DPP row and lane inside it
     const uint32_t G = R.G;
-    const uint32_t D = (uint32_t)(rows * P);
+    const uint32_t D = (uint32_t)(rows * P * RND);
     // rows run frequency lines: one per domain, or (two colours) the four active
     // octants of each domain, lines 4k .. 4k + 3 of domain k
     const uint32_t lpd = LPD ? (uint32_t)LPD : g.lpd, NL = g.K * lpd;  // LPD = 0: read at run time
@@ -267,6 +284,56 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                 sh.rk[i] = i < nvalid ? m : 0.0;
             }
             __syncthreads();
+        } else if constexpr (RND > 1) {
+            // --- steps 1 and 4a, wide mode: the moments of every round's lines (the
+            // class planes are derived again for the selection)
+#pragma unroll 1
+            for (int r = 0; r < RND; ++r) {
+                Raw<H> raw[P];
+#pragma unroll
+                for (int pp = 0; pp < P; ++pp) {
+                    const uint32_t ld = (uint32_t)((r * P + pp) * rows + row);
+                    const bool valid = ld < nvalid;
+                    load_octant<H>(g, line_dom(kbase + ld), line_oct(kbase + ld, s), valid, l,
+                                   sh.nbdom[valid ? ld : 0], raw[pp]);
+                }
+#pragma unroll
+                for (int pp = 0; pp < P; ++pp) {
+                    const uint32_t ld = (uint32_t)((r * P + pp) * rows + row);
+                    Planes<H> pw;
+                    uint32_t m[13];
+#pragma unroll
+                    for (int i = 0; i < 13; ++i) m[i] = 0;
+                    compute_octant<H, true>(raw[pp], ld < nvalid, l, sh.zbuf[row], pw, m);
+                    uint32_t mp[7];
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) mp[i] = row_scan(m[2 * i] | (m[2 * i + 1] << 16));
+                    mp[6] = row_scan(m[12]);
+                    if (l == 15) {
+#pragma unroll
+                        for (int i = 0; i < 6; ++i) {
+                            sh.mom[ld][2 * i] = mp[i] & 0xFFFFu;
+                            sh.mom[ld][2 * i + 1] = mp[i] >> 16;
+                        }
+                        sh.mom[ld][12] = mp[6];
+                    }
+                }
+            }
+            __syncthreads();
+            for (uint32_t i = tid; i < D; i += nthr) {
+                uint32_t mm[13], hc[14];
+                for (int c = 0; c < 13; ++c) mm[c] = sh.mom[i][c];
+                hist_from_moments(mm, g.h3, hc);
+                double a = 0.0;
+                for (int c = 0; c < 14; ++c) {
+                    double term = (double)hc[c] * sh.r[c];
+                    a = a + term;
+                    sh.acc[i][c] = a;
+                    sh.hist[i][c] = hc[c];
+                }
+                sh.rk[i] = i < nvalid ? a : 0.0;
+            }
+            __syncthreads();
         } else {
             // --- steps 1 and 4a: class planes and moments of the active octants
             // (the words of every pass in flight at once; each pass's raw words
@@ -356,7 +423,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         // lane pp of each row draws for the row's line of pass pp
         U4 dw;
         {
-            const uint32_t kd = kbase + (uint32_t)((l < P ? l : 0) * rows + row);
+            const uint32_t kd = kbase + (uint32_t)((l < P * RND ? l : 0) * rows + row);
             dw = philox10((uint32_t)n, (uint32_t)(n >> 32), line_dom(kd), (uint32_t)line_oct(kd, s), g.seed);
         }
         // sites of class c on line ld
@@ -364,7 +431,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             return INC ? hcount(sh.histp[ld][s], c) : sh.hist[ld][c];
         };
         uint32_t cpred = 0;  // per pass: predicted class + 1, five bits each
-        {
+        if constexpr (RND == 1) {
             const double Rspec = bound ? g.rbound : sh.rpred[s];
 #pragma unroll
             for (int pp = 0; pp < P; ++pp) {
@@ -420,7 +487,33 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         if (sh.abort) break;
         const double Rmax = bound ? g.rbound : sh.rmax;
 
-        if (!bound) {
+        if constexpr (RND > 1) {
+            // --- steps 3, 4 and 4b, wide mode: every round's class planes from its
+            // words, then the selection with the true R_max
+#pragma unroll 1
+            for (int r = 0; r < RND; ++r) {
+                Raw<H> raw[P];
+#pragma unroll
+                for (int pp = 0; pp < P; ++pp) {
+                    const uint32_t ld = (uint32_t)((r * P + pp) * rows + row);
+                    const bool valid = ld < nvalid;
+                    load_octant<H>(g, line_dom(kbase + ld), line_oct(kbase + ld, s), valid, l,
+                                   sh.nbdom[valid ? ld : 0], raw[pp]);
+                }
+#pragma unroll
+                for (int pp = 0; pp < P; ++pp) {
+                    const int j = r * P + pp;
+                    const uint32_t ld = (uint32_t)(j * rows + row);
+                    const bool valid = ld < nvalid;
+                    Planes<H> pw;
+                    uint32_t m[13];
+                    compute_octant<H, false>(raw[pp], valid, l, sh.zbuf[row], pw, m);
+                    const uint32_t ux = row_lane(dw.x, j), uy = row_lane(dw.y, j), uz = row_lane(dw.z, j);
+                    const int cs = row_class(sh.acc[ld], valid, unit53(ux, uy) * Rmax, l, row);
+                    select_site<H>(pw, cs, cs >= 0 ? sh.hist[ld][cs] : 0u, uz, l, &sh.selq[ld], st);
+                }
+            }
+        } else if (!bound) {
             // the true R_max: rows whose class differs select again
             if (tid == 0) sh.rpred[s] = Rmax;
 #pragma unroll
@@ -656,6 +749,14 @@ __global__ void __launch_bounds__(BLOCK) k_persistent(Replica R) {
     persistent_body<H, P, BLOCK, INC, LPD>(R, blockIdx.x, sh);
 }
 
+// One lattice in the wide mode (octant edge 16; RND rounds of four passes, 128 RND
+// lines per workgroup).
+template <int RND, int LPD>
+__global__ void __launch_bounds__(512) k_persistent_wide(Replica R) {
+    __shared__ PersistSharedWide<RND> sh;
+    persistent_body<16, 4, 512, false, LPD, RND, PersistSharedWide<RND>>(R, blockIdx.x, sh);
+}
+
 // Many independent lattices in one launch: each workgroup finds its lattice by
 // its workgroup index; lattices never wait for one another.
 template <int H, int P, int BLOCK, bool INC>
@@ -715,9 +816,24 @@ static void *kernel_of(bool batch, bool inc, uint32_t lpd) {
     return lpd == 4 ? reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false, 4>)
                     : reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false, 1>);
 }
+// The wide mode's rounds for one lattice: 1 (passes only), 2 or 4 (octant edge 16,
+// re-binning engine).
+static int max_rounds(int h, bool inc) { return h == 16 && !inc ? 4 : 1; }
+
 // Batches use the re-binning kernel (lines per domain read at run time).
-static void *select_kernel(int h, int P, int block, bool batch = false, bool inc = false, uint32_t lpd = 1) {
+static void *select_kernel(int h, int P, int block, bool batch = false, bool inc = false, uint32_t lpd = 1,
+                           int rnd = 1) {
     if (batch && inc) return nullptr;
+    if (rnd > 1) {
+        if (batch || inc || h != 16 || block != 512 || P != 4) return nullptr;
+        if (rnd == 2)
+            return lpd == 4 ? reinterpret_cast<void *>(&k_persistent_wide<2, 4>)
+                            : reinterpret_cast<void *>(&k_persistent_wide<2, 1>);
+        if (rnd == 4)
+            return lpd == 4 ? reinterpret_cast<void *>(&k_persistent_wide<4, 4>)
+                            : reinterpret_cast<void *>(&k_persistent_wide<4, 1>);
+        return nullptr;
+    }
     if (h == 16 && block == 512)
         return P == 1   ? kernel_of<16, 1, 512>(batch, inc, lpd)
                : P == 2 ? kernel_of<16, 2, 512>(batch, inc, lpd)
@@ -742,10 +858,10 @@ bool persistent_supported(const Geom &g, const spkmc_params &p, bool inc, std::s
                   : "this engine runs variants 0, RMAX_BOUND and TWO_COLOURS";
         return false;
     }
-    const int rows = persist_rows(g.h, inc), pmax = persist_max_passes(g.h, inc);
+    const int rows = persist_rows(g.h, inc), pmax = persist_max_passes(g.h, inc) * max_rounds(g.h, inc);
     const int pc = p.wg_domains / rows;
     if (p.wg_domains && (p.wg_domains % rows || pc > pmax || (pc & (pc - 1)))) {
-        why = "wg_domains must be " + std::to_string(rows) + " times 1, 2" + (pmax == 4 ? " or 4" : "") +
+        why = "wg_domains must be " + std::to_string(rows) + " times a power of two up to " + std::to_string(pmax) +
               " for this octant edge and engine";
         return false;
     }
@@ -762,16 +878,17 @@ hipError_t persistent_configure(const Geom &g, const spkmc_params &p, bool inc, 
     if (e != hipSuccess) return e;
     const int rows = persist_rows(g.h, inc), pmax = persist_max_passes(g.h, inc);
     block = rows * 16;
-    // the fewest passes whose workgroups are all resident at once (or the
-    // requested domains per workgroup)
-    for (int P = 1; P <= pmax; P <<= 1) {
-        if (p.wg_domains && p.wg_domains != rows * P) continue;
-        void *kern = select_kernel(g.h, P, block, false, inc, g.lpd);
+    // the fewest passes (then rounds of passes) whose workgroups are all resident
+    // at once (or the requested lines per workgroup)
+    for (int pc = 1; pc <= pmax * max_rounds(g.h, inc); pc <<= 1) {
+        const int P = pc < pmax ? pc : pmax;
+        if (p.wg_domains && p.wg_domains != rows * pc) continue;
+        void *kern = select_kernel(g.h, P, block, false, inc, g.lpd, pc / P);
         if (!kern) return hipErrorInvalidValue;
         int occ = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, 0);
         if (e != hipSuccess) return e;
-        const uint64_t D = (uint64_t)rows * P, G = ((uint64_t)g.K * g.lpd + D - 1) / D;
+        const uint64_t D = (uint64_t)rows * pc, G = ((uint64_t)g.K * g.lpd + D - 1) / D;
         if (occ > 0 && G <= (uint64_t)occ * cus && G <= (uint64_t)kMaxGrid) {
             grid = (int)G;
             wg_domains = (int)D;
@@ -795,8 +912,8 @@ PersistScratch scratch_of(const Geom &g, int G) {
 hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid, int block,
                              int wg_domains, bool inc, hipStream_t stream) {
     PersistScratch xs = scratch_of(g, grid);
-    int P = wg_domains / (block / 16);
-    void *kern = select_kernel(g.h, P, block, false, inc, g.lpd);
+    const int pc = wg_domains / (block / 16), P = pc < 4 ? pc : 4;  // passes, then rounds of four passes
+    void *kern = select_kernel(g.h, P, block, false, inc, g.lpd, pc / P);
     if (!kern) return hipErrorInvalidValue;
     const uint64_t ndh = inc ? (uint64_t)g.K * 16 : 0;
     uint64_t blocks = ((uint64_t)grid + 255) / 256, bdh = (ndh + 255) / 256;
