@@ -511,8 +511,8 @@ def main():
                      "traffic_source": None if traffic is None else traffic_rec["path"],
                      "valu": measured_valu(w["name"], kernel) if launches == 1 and not args.variant else None,
                      # the lower bound of the bytes a cycle must move: the active octants'
-                     # own bits only (class masks without a halo), K h^3 / 8
-                     "frac_lower_bound_bytes": (info["K"] * info["h"] ** 3 / 8.0) * args.steps / secs / 1e9
+                     # own bits only (class masks without a halo), K l h^3 / 8 (l active octants per domain)
+                     "frac_lower_bound_bytes": (info["K"] * lpd * info["h"] ** 3 / 8.0) * args.steps / secs / 1e9
                      / HBM_PEAK_GBS},
     }
     if not args.no_cpu_baseline:

@@ -170,8 +170,10 @@ typedef struct spkmc_info {
     uint64_t K;              /* number of domains                                */
     uint64_t N;              /* number of sites                                  */
     uint64_t state_bytes;    /* bytes of device state                            */
-    double bytes_per_cycle;  /* algorithmic bytes per cycle: K ((h^3 + 6 h^2)/8 + 8),
-                                plus K 2 x 112 for the slab engine's count words */
+    double bytes_per_cycle;  /* algorithmic bytes per cycle: K l ((h^3 + 6 h^2)/8 + 8)
+                                with l active octants per domain (1; 4 with
+                                TWO_COLOURS), plus K 2 x 112 for the slab engine's
+                                count words                                       */
 } spkmc_info;
 
 /* Device bytes needed for these parameters; 0 if the parameters are invalid. */

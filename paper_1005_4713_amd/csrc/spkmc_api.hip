@@ -511,7 +511,8 @@ spkmc_status spkmc_query(const spkmc_ctx *c, spkmc_info *out) {
     out->N = c->g.N;
     out->state_bytes = c->spin_off + c->spin_bytes;
     double h = c->g.h;
-    out->bytes_per_cycle = (double)c->g.K * ((h * h * h + 6.0 * h * h) / 8.0 + 8.0);
+    // every frequency line (an active octant: one per domain, four with two colours)
+    out->bytes_per_cycle = (double)c->g.K * c->g.lpd * ((h * h * h + 6.0 * h * h) / 8.0 + 8.0);
     // slab engine: the active octant's 28 count words are read and written back too
     if (c->engine == SPKMC_ENGINE_SLAB) out->bytes_per_cycle += (double)c->g.K * 2.0 * 28.0 * 4.0;
     return SPKMC_OK;
