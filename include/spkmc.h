@@ -192,12 +192,14 @@ size_t spkmc_state_bytes(const spkmc_params *p);
 spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, void *hip_stream,
                         spkmc_ctx **out);
 
-/* Enqueue `ncycles` cycles.  Every obs_every cycles (counted by the absolute
+/* Enqueue `ncycles` cycles of the synchronous method (Sec. 3.1 steps 1-6, with
+ * the sublattice steps 4a/4b of Sec. 3.2).  Every obs_every cycles (counted by the absolute
  * cycle number; 0 = never) a record of the state after that cycle is appended
  * to the device ring of record_cap entries. */
 spkmc_status spkmc_run(spkmc_ctx *ctx, uint64_t ncycles, uint32_t obs_every);
 
-/* Synchronise the stream and return the current state. */
+/* Synchronise the stream and return the current state: counters, clock (Sec. 3.1
+ * step 5), M and B, the energy of eq. 1, m of eq. 4 and the utilisation of eq. 8. */
 spkmc_status spkmc_observables(spkmc_ctx *ctx, spkmc_obs *out);
 
 /* Synchronise and copy the most recent min(cap, recorded, record_cap) records,
@@ -211,7 +213,8 @@ spkmc_status spkmc_copy_spins(spkmc_ctx *ctx, int8_t *host, size_t n);
  * counters, clock and cycle number are kept.  Synchronises. */
 spkmc_status spkmc_set_spins(spkmc_ctx *ctx, const int8_t *host, size_t n);
 
-/* The 14 FP64 rates c = 0..13 the library uses for these parameters. */
+/* The 14 FP64 rates c = 0..13 the library uses for these parameters (eq. 3 in its
+ * detailed-balance form, or Metropolis; flip energies from eq. 1). */
 spkmc_status spkmc_rate_table(const spkmc_params *p, double out[14]);
 
 /* Checkpoint: with host == NULL, *n receives the blob size.  Otherwise the
@@ -242,7 +245,9 @@ typedef struct spkmc_batch_info {
 size_t spkmc_batch_workspace_bytes(size_t n);
 
 /* Run ncycles[i] cycles (0 = skip) on each of n contexts in one cooperative
- * launch on their common stream.  The lattices stay independent: each keeps its
+ * launch on their common stream.  Each lattice runs the cycle of spkmc_run
+ * (Sec. 3.1); running many lattices in one launch is a scheduling choice of this
+ * library, not an operation of the method.  The lattices stay independent: each keeps its
  * own clock, R_max, random streams and records, and the result of every
  * lattice is bit-identical to running it alone with spkmc_run.  All contexts
  * must use the PACKED layout with the same octant edge (8 or 16) and the same
@@ -282,7 +287,9 @@ void spkmc_batch_graph_destroy(spkmc_batch_graph *graph);
 /* ------------------------------------------------------------------------- */
 /* Serving: a request loop with continuous batching.                          */
 /* ------------------------------------------------------------------------- */
-/* A server owns a caller-provided device pool and a stream.  Requests (one
+/* Serving is a scheduling layer of this library, not an operation of the method:
+ * every request runs the cycle of spkmc_run (Sec. 3.1).
+ * A server owns a caller-provided device pool and a stream.  Requests (one
  * lattice each: spkmc_params, a cycle count and an observation interval) are
  * queued in FIFO order and admitted while a slot is free and their footprint
  * (spkmc_state_bytes, first fit in the pool) fits; the lattice and its clock
