@@ -102,3 +102,26 @@ def test_server_errors(spkmc):
     with pytest.raises(spkmc.SpkmcError):
         srv.poll(rid)
     srv.close()
+
+
+def test_served_wide_lattice_runs_alone(spkmc):
+    """A lattice with more lines than one batch launch holds (two colours at 1024^3:
+    131 072 lines) is served alone through spkmc_run, which takes the persistent
+    kernel's wide mode, beside a small batched request; both results equal their
+    solo runs (the server's 20-cycle macro-steps against one 40-cycle run)."""
+    print("serve: wide lattice beside a batched one", flush=True)
+    big = spkmc.state_bytes(spkmc.make_params(1024, 32, variant=2, record_cap=16))
+    srv = spkmc.Server(big + (256 << 20), macro_cycles=20, max_live=4, inflight=2)
+    rb = srv.submit(1024, 32, 40, obs_every=10, variant=2, T=4.5115, seed=8, record_cap=16)
+    rs = srv.submit(64, 16, 40, obs_every=10, T=4.5115, seed=9, record_cap=16)
+    st = srv.drain()
+    assert st["done"] == 2 and st["failed"] == 0
+    got_big, got_small = srv.poll(rb)["state_tuple"], srv.poll(rs)["state_tuple"]
+    srv.close()
+    a = spkmc.Sim(1024, 32, variant=2, T=4.5115, seed=8, record_cap=16)
+    assert a.info()["engine"] == spkmc.ENGINES["persistent"] and a.info()["wg_domains"] == 512
+    a.run(40, obs_every=10)
+    assert got_big == a.state()
+    b = spkmc.Sim(64, 16, T=4.5115, seed=9, record_cap=16)
+    b.run(40, obs_every=10)
+    assert got_small == b.state()
