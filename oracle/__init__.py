@@ -6,5 +6,5 @@ with ctypes and adds the L = 2 exact enumeration in ``enumerate2``.
 """
 from .oracle import (  # noqa: F401
     Params, Record, Sim, Bkl, lib, philox, u53, uopen52, idx, rate_table, select,
-    observables, site_class, init_spins,
+    observables, site_class, init_spins, set_threads, get_threads,
 )

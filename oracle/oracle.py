@@ -65,6 +65,8 @@ def _load():
         "orc_observables": (None, [i8p, C.c_int32, i64p, i64p]),
         "orc_site_class": (C.c_int32, [i8p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
         "orc_init_spins": (None, [i8p, C.c_int64, C.c_uint64, C.c_int32]),
+        "orc_set_threads": (None, [C.c_int32]),
+        "orc_get_threads": (C.c_int32, []),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -136,6 +138,16 @@ def init_spins(L, seed, init=0):
     out = np.empty(L ** 3, dtype=np.int8)
     lib.orc_init_spins(_p(out, C.c_int8), L ** 3, seed, init)
     return out
+
+
+def set_threads(n):
+    """Threads of the per-domain loops of a cycle (1 = the plain serial loops;
+    any count gives the same trajectory bit for bit)."""
+    lib.orc_set_threads(int(n))
+
+
+def get_threads():
+    return lib.orc_get_threads()
 
 
 def make_params(L, d, J=1.0, H=0.0, T=4.5115, seed=1, rates=0, init=0, colours=8,

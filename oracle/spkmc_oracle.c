@@ -8,7 +8,14 @@
  * rejection-free BKL/n-fold simulator used as the statistical reference.
  *
  * Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
- * load this file.  It shares no code, header, table or constant generator with
+ * load this file.
+ *
+ * By default everything runs on one thread.  orc_set_threads(n > 1) runs the
+ * per-domain loops of one cycle (the frequency lines of step 1 and the
+ * decisions of steps 3-4b) as an OpenMP parallel-for; within a cycle the
+ * domains read only spins no other domain writes (same-coloured octants never
+ * touch), and the flips are still applied after every decision, in line
+ * order, so the trajectory is bit-identical for every thread count.  It shares no code, header, table or constant generator with
  * the GPU library; the only thing both sides agree on is the published
  * definition of Philox4x32-10 and the readings of the paper listed below.
  *
@@ -65,6 +72,11 @@
 #include <string.h>
 
 #define ORC_EXPORT __attribute__((visibility("default")))
+
+/* threads of the per-domain loops (1: plain serial loops) */
+static int orc_threads = 1;
+ORC_EXPORT void orc_set_threads(int32_t n) { orc_threads = n > 1 ? n : 1; }
+ORC_EXPORT int32_t orc_get_threads(void) { return orc_threads; }
 
 /* ------------------------------------------------------------------------- */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11 "Parallel random numbers: */
@@ -288,6 +300,7 @@ typedef struct {
     int64_t *flip_site;
     int8_t *flip_old;
     int8_t *flip_a;
+    uint8_t *flip_fire; /* decide-then-apply: line f fires this cycle */
     uint32_t *perm;
 } orc_sim;
 
@@ -376,10 +389,12 @@ ORC_EXPORT orc_sim *orc_sim_new(const orc_params *p) {
     S->flip_site = (int64_t *)malloc(sizeof(int64_t) * nl);
     S->flip_old = (int8_t *)malloc(nl);
     S->flip_a = (int8_t *)malloc(nl);
+    S->flip_fire = (uint8_t *)malloc(nl);
     S->perm = (uint32_t *)malloc(sizeof(uint32_t) * nl);
-    if (!S->g.spin || !S->hist || !S->R || !S->flip_site || !S->flip_old || !S->flip_a || !S->perm) {
+    if (!S->g.spin || !S->hist || !S->R || !S->flip_site || !S->flip_old || !S->flip_a || !S->flip_fire ||
+        !S->perm) {
         free(S->g.spin); free(S->hist); free(S->R); free(S->flip_site);
-        free(S->flip_old); free(S->flip_a); free(S->perm); free(S);
+        free(S->flip_old); free(S->flip_a); free(S->flip_fire); free(S->perm); free(S);
         return NULL;
     }
     init_spins(S->g.spin, S->N, p->seed, p->init);
@@ -390,7 +405,7 @@ ORC_EXPORT orc_sim *orc_sim_new(const orc_params *p) {
 ORC_EXPORT void orc_sim_free(orc_sim *S) {
     if (!S) return;
     free(S->g.spin); free(S->hist); free(S->R); free(S->flip_site);
-    free(S->flip_old); free(S->flip_a); free(S->perm);
+    free(S->flip_old); free(S->flip_a); free(S->flip_fire); free(S->perm);
     free(S);
 }
 
@@ -425,6 +440,7 @@ static double spkmc_cycle(orc_sim *S) {
     const uint32_t nl = S->K * S->A; /* frequency lines (subdomains) of this cycle */
 
     /* step 1: frequency line of every active region (line f = A k + a) */
+#pragma omp parallel for num_threads(orc_threads) if (orc_threads > 1) schedule(static)
     for (uint32_t f = 0; f < nl; ++f) {
         uint32_t k = f / S->A;
         int s = line_octant(S, colour, f % S->A);
@@ -438,9 +454,10 @@ static double spkmc_cycle(orc_sim *S) {
         for (uint32_t f = 0; f < nl; ++f)
             if (S->R[f] > Rmax) Rmax = S->R[f];
     } else if (S->p.rmax_scope == 1) {
-        uint32_t h2[14];
+#pragma omp parallel for num_threads(orc_threads) if (orc_threads > 1) schedule(static) reduction(max : Rmax)
         for (uint32_t k = 0; k < S->K; ++k)
             for (int c = 0; c < (S->S == 1 ? 1 : 8); ++c) {
+                uint32_t h2[14];
                 bin_region(S, k, c, h2);
                 double Rc = line_total(h2, S->r);
                 if (Rc > Rmax) Rmax = Rc;
@@ -453,53 +470,76 @@ static double spkmc_cycle(orc_sim *S) {
 
     /* steps 3, 4, 4b: in every line an event with probability r / R_max */
     uint32_t nfire = 0;
-    for (uint32_t f = 0; f < nl; ++f) S->perm[f] = f;
-    if (S->p.order == 2) {
-        /* shuffled order: any permutation must give the same result */
-        uint64_t st = 0x9E3779B97F4A7C15ull ^ n;
-        for (uint32_t i = nl; i > 1; --i) {
-            st = st * 6364136223846793005ull + 1442695040888963407ull;
-            uint32_t jx = (uint32_t)((st >> 33) % i);
-            uint32_t tmp = S->perm[i - 1];
-            S->perm[i - 1] = S->perm[jx];
-            S->perm[jx] = tmp;
+    if (S->p.order == 0) {
+        /* decide every line first (each line reads only its own region and
+         * halo), then apply the flips in line order (step 6) */
+        uint64_t fails = 0;
+#pragma omp parallel for num_threads(orc_threads) if (orc_threads > 1) schedule(static) reduction(+ : nfire, fails)
+        for (uint32_t f = 0; f < nl; ++f) {
+            S->flip_fire[f] = 0;
+            uint32_t k = f / S->A;
+            int s = line_octant(S, colour, f % S->A);
+            uint32_t dw[4];
+            philox_words(S->p.seed, nlo, nhi, k, (uint32_t)s, dw);
+            double u = orc_u53(dw[0], dw[1]);
+            int32_t c;
+            uint32_t j;
+            if (!orc_select(&S->hist[(size_t)f * 14], S->r, Rmax, u, dw[2], &c, &j)) continue; /* null */
+            int a = 0;
+            int64_t site = find_site(S, k, s, c, j, &a);
+            if (site < 0) {
+                fails++;
+                continue;
+            }
+            S->flip_fire[f] = 1;
+            S->flip_site[f] = site;
+            S->flip_old[f] = S->g.spin[site];
+            S->flip_a[f] = (int8_t)a;
+            ++nfire;
         }
-    }
-    for (uint32_t ii = 0; ii < nl; ++ii) {
-        uint32_t f = S->perm[ii];
-        uint32_t k = f / S->A;
-        int s = line_octant(S, colour, f % S->A);
-        uint32_t dw[4];
-        philox_words(S->p.seed, nlo, nhi, k, (uint32_t)s, dw);
-        double u = orc_u53(dw[0], dw[1]);
-        int32_t c;
-        uint32_t j;
-        const uint32_t *hk = &S->hist[(size_t)f * 14];
-        if (S->p.order != 0) {
+        S->check_fail += fails;
+        for (uint32_t f = 0; f < nl; ++f)
+            if (S->flip_fire[f]) flip_apply(S, S->flip_site[f], S->flip_old[f], S->flip_a[f]);
+    } else {
+        /* apply each flip at once, in domain order (1) or a shuffled order (2) */
+        for (uint32_t f = 0; f < nl; ++f) S->perm[f] = f;
+        if (S->p.order == 2) {
+            /* shuffled order: any permutation must give the same result */
+            uint64_t st = 0x9E3779B97F4A7C15ull ^ n;
+            for (uint32_t i = nl; i > 1; --i) {
+                st = st * 6364136223846793005ull + 1442695040888963407ull;
+                uint32_t jx = (uint32_t)((st >> 33) % i);
+                uint32_t tmp = S->perm[i - 1];
+                S->perm[i - 1] = S->perm[jx];
+                S->perm[jx] = tmp;
+            }
+        }
+        for (uint32_t ii = 0; ii < nl; ++ii) {
+            uint32_t f = S->perm[ii];
+            uint32_t k = f / S->A;
+            int s = line_octant(S, colour, f % S->A);
+            uint32_t dw[4];
+            philox_words(S->p.seed, nlo, nhi, k, (uint32_t)s, dw);
+            double u = orc_u53(dw[0], dw[1]);
+            int32_t c;
+            uint32_t j;
+            const uint32_t *hk = &S->hist[(size_t)f * 14];
             /* flips already applied in this cycle must not have changed this
              * region or its halo: recompute and compare */
             uint32_t again[14];
             bin_region(S, k, s, again);
             if (memcmp(again, hk, sizeof(again)) != 0) S->check_fail++;
-        }
-        if (!orc_select(hk, S->r, Rmax, u, dw[2], &c, &j)) continue; /* null event */
-        int a = 0;
-        int64_t site = find_site(S, k, s, c, j, &a);
-        if (site < 0) {
-            S->check_fail++;
-            continue;
-        }
-        if (S->p.order == 0) {
-            S->flip_site[nfire] = site;
-            S->flip_old[nfire] = S->g.spin[site];
-            S->flip_a[nfire] = (int8_t)a;
-        } else {
+            if (!orc_select(hk, S->r, Rmax, u, dw[2], &c, &j)) continue; /* null event */
+            int a = 0;
+            int64_t site = find_site(S, k, s, c, j, &a);
+            if (site < 0) {
+                S->check_fail++;
+                continue;
+            }
             flip_apply(S, site, S->g.spin[site], a);
+            ++nfire;
         }
-        ++nfire;
     }
-    if (S->p.order == 0)
-        for (uint32_t f = 0; f < nfire; ++f) flip_apply(S, S->flip_site[f], S->flip_old[f], S->flip_a[f]);
 
     /* step 5: common time increment (reading R5) */
     double dt = -log(ut) / ((double)S->S * Rmax);

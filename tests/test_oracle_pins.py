@@ -227,6 +227,43 @@ def test_frequency_line_probabilities_exact():
             assert js.min() >= 4096 // n - 1 and js.max() <= 4096 // n + 2
 
 
+# --------------------------------------------------------------------------- random start
+@pytest.mark.parametrize("seed", [1, 2, 42])
+def test_random_start_is_iid_half(seed):
+    """init = random gives iid +-1 spins with p = 1/2 (the workloads' random
+    start): the magnetisation, the correlation at every lag that the block and
+    word structure of the draws could repeat at (1, the 32-bit word, the
+    128-bit block, one x row, one plane), the nearest-neighbour correlation on
+    the periodic lattice along each axis, the up count of every 128-site block
+    against Binomial(128, 1/2), and no block repeated."""
+    from scipy import stats
+    L = 64
+    N = L ** 3
+    s = oracle.init_spins(L, seed, 0).astype(np.float64)
+    assert set(np.unique(s)) == {-1.0, 1.0}
+    lim = 5.0 / math.sqrt(N)
+    assert abs(s.mean()) < lim
+    for lag in (1, 2, 31, 32, 33, 64, 96, 127, 128, 129, 256, 512, L, L * L, 4096):
+        assert abs(np.mean(s[:-lag] * s[lag:])) < 5.0 / math.sqrt(N - lag), lag
+    cube = s.reshape(L, L, L)  # [z, y, x]
+    for ax in range(3):
+        assert abs(np.mean(cube * np.roll(cube, 1, axis=ax))) < lim, ax
+    blocks = (s.reshape(-1, 128) > 0)
+    ups = blocks.sum(axis=1)
+    obs = np.bincount(ups, minlength=129)
+    # pool the tails so every expected count is at least 5
+    pmf = stats.binom.pmf(np.arange(129), 128, 0.5)
+    lo, hi = 46, 82
+    o = np.concatenate([[obs[:lo].sum()], obs[lo:hi + 1], [obs[hi + 1:].sum()]])
+    e = np.concatenate([[pmf[:lo].sum()], pmf[lo:hi + 1], [pmf[hi + 1:].sum()]]) * len(ups)
+    assert stats.chisquare(o, e).pvalue > 1e-4
+    packed = np.packbits(blocks, axis=1)
+    assert len({row.tobytes() for row in packed}) == len(packed)  # no Philox block repeats
+    # a different key gives an uncorrelated lattice
+    s2 = oracle.init_spins(L, seed + 1000, 0).astype(np.float64)
+    assert abs(np.mean(s * s2)) < lim
+
+
 # --------------------------------------------------------------------------- cycle invariants
 @pytest.mark.parametrize("L,d,init", [(16, 8, 0), (16, 4, 1), (12, 6, 2), (8, 2, 0)])
 def test_cycle_invariants(L, d, init):
@@ -243,6 +280,24 @@ def test_cycle_invariants(L, d, init):
         prev = (fired, nulls, t)
     M, B = oracle.observables(sim.spins())
     assert (M, B) == (recs[-1][4], recs[-1][5])
+
+
+@pytest.mark.parametrize("colours,scope", [(8, 0), (2, 0), (8, 1), (2, 2)])
+def test_thread_count_independence(colours, scope):
+    """The opt-in parallel-for over domains gives the single-threaded
+    trajectory bit for bit (records and final spins)."""
+    out = []
+    for nt in (1, 4):
+        oracle.set_threads(nt)
+        try:
+            sim = oracle.Sim(L=16, d=4, seed=19, H=0.05, colours=colours, rmax_scope=scope, check=1)
+            recs = sim.run(200, obs_every=7)
+            assert sim.check_failures() == 0
+            out.append((recs, sim.spins()))
+        finally:
+            oracle.set_threads(1)
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1])
 
 
 def test_order_independence():

@@ -91,27 +91,60 @@ def _j0_curve(make, grid, runs):
     return np.array(ms)
 
 
+def _j0_check(curves, want, N):
+    """Mean of the runs against the closed form.  Every run shares one clock
+    over all its domains, so the run-to-run scatter of m(t) exceeds that of N
+    independent spins; the error bar is the larger of the empirical standard
+    error and the independent-spin one."""
+    runs = curves.shape[0]
+    se = np.maximum(curves.std(axis=0, ddof=1), np.sqrt((1 - want ** 2) / N)) / math.sqrt(runs)
+    dev = np.abs(curves.mean(axis=0) - want)
+    assert np.all(dev < 5 * se), (curves.mean(axis=0), want, se)
+
+
+J0_T, J0_H = 1.0, 0.3
+J0_GRID = np.array([0.05, 0.2, 0.5, 1.0, 2.0, 4.0])
+
+
+def _j0_want(rates):
+    beta = 1.0 / J0_T
+    minf = math.tanh(beta * J0_H)
+    gamma = 1.0 if rates == 0 else 1.0 + math.exp(-2 * beta * abs(J0_H))
+    return minf + (1 - minf) * np.exp(-gamma * J0_GRID)
+
+
 @pytest.mark.parametrize("rates", [0, 1])
 def test_j0_relaxation_closed_form(rates):
     """J = 0, field H, from all +1: every spin is an independent two-state
     process, m(t) = m_inf + (1 - m_inf) exp(-Gamma t) with m_inf = tanh(beta H),
     Gamma = 1 (Glauber) or 1 + exp(-2 beta |H|) (Metropolis).  A wrong colour
     factor in the clock would change Gamma eightfold."""
-    T, H = 1.0, 0.3
-    beta = 1.0 / T
-    minf = math.tanh(beta * H)
-    gamma = 1.0 if rates == 0 else 1.0 + math.exp(-2 * beta * abs(H))
-    grid = np.array([0.05, 0.2, 0.5, 1.0, 2.0, 4.0])
-    want = minf + (1 - minf) * np.exp(-gamma * grid)
-    N = 32 ** 3
-    runs = 4
-    sd = np.sqrt((1 - want ** 2) / N / runs)
-    sp = _j0_curve(lambda r: oracle.Sim(L=32, d=16, J=0.0, H=H, T=T, rates=rates, init=1, seed=100 + r),
-                   grid, runs).mean(axis=0)
-    assert np.all(np.abs(sp - want) < 5 * sd + 1e-4), (sp, want)
-    bk = _j0_curve(lambda r: oracle.Bkl(L=32, J=0.0, H=H, T=T, rates=rates, init=1, seed=200 + r),
-                   grid, runs).mean(axis=0)
-    assert np.all(np.abs(bk - want) < 5 * sd + 1e-4), (bk, want)
+    want = _j0_want(rates)
+    N, runs = 32 ** 3, 8
+    _j0_check(_j0_curve(lambda r: oracle.Sim(L=32, d=16, J=0.0, H=J0_H, T=J0_T, rates=rates, init=1,
+                                             seed=100 + r), J0_GRID, runs), want, N)
+    _j0_check(_j0_curve(lambda r: oracle.Bkl(L=32, J=0.0, H=J0_H, T=J0_T, rates=rates, init=1, seed=200 + r),
+                        J0_GRID, runs), want, N)
+
+
+@pytest.mark.parametrize("colours,scope", [(8, 1), (8, 2), (2, 0), (2, 1), (2, 2)])
+def test_j0_relaxation_variant_clocks(colours, scope):
+    """The clock of every variant (Sec. 3.1 step 5 with S colours, reading R5):
+    two colours (S = 2, four lines per domain), R_max over all octants, and the
+    fixed bound R'_max.  At J = 0 the drift of M is linear in the spins, so
+    d<M>/dt takes the physical value for any R_max rule that the clock divides
+    out: m(t) follows the closed form exactly in expectation.  S = 8 left in
+    for two colours would slow the decay fourfold; a clock that ignored the
+    larger all-octant or bound R_max would speed it up."""
+    want = _j0_want(0)
+    N, runs = 32 ** 3, 8
+    curves = _j0_curve(lambda r: oracle.Sim(L=32, d=16, J=0.0, H=J0_H, T=J0_T, init=1, seed=300 + r,
+                                            colours=colours, rmax_scope=scope), J0_GRID, runs)
+    _j0_check(curves, want, N)
+    # the same runs are far from the curve of a clock off by a factor of four
+    minf = math.tanh(J0_H / J0_T)
+    wrong = minf + (1 - minf) * np.exp(-4.0 * J0_GRID)
+    assert abs(curves.mean(axis=0)[2] - wrong[2]) > 0.1
 
 
 def test_spkmc_bias_within_serial_deviation():
