@@ -201,10 +201,10 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     }
 
     DevState *st = g.st;
-    // launch-start totals (read before any workgroup can publish its first slot,
-    // hence before any workgroup can fold its own totals in at the end)
-    const uint64_t fired0 = st->fired, nulls0 = st->nulls;
-    const int64_t M0 = st->M, B0 = st->B;
+    // launch-start totals (the prep kernel's copy)
+    const StartTotals st0 = start_totals(xs);
+    const uint64_t fired0 = st0.fired, nulls0 = st0.nulls;
+    const int64_t M0 = st0.M, B0 = st0.B;
     double t = st->t;  // every workgroup advances the same clock
     long long myF = 0, mydM = 0, mydB = 0;  // this thread's share since launch start
     uint32_t rec_index = 0;                  // records produced in this launch
@@ -775,23 +775,32 @@ __global__ void __launch_bounds__(BLOCK) k_persistent_batch(const Replica *__res
 }
 
 // Before a launch: slots carry the generation of no cycle of this launch yet,
-// flags the start cycle.
-__device__ __forceinline__ void prep_one(const PersistScratch &xs, uint32_t G, uint64_t n0, uint32_t i) {
+// flags the start cycle; the counters at launch start are copied.
+__device__ __forceinline__ void prep_one(const PersistScratch &xs, uint32_t G, uint64_t n0, uint32_t i,
+                                         const DevState *st) {
     // bank b first serves cycle nb (n0 or n0 + 1, nb & 1 == b): mark it "not yet"
     for (uint64_t nb = n0; nb < n0 + 2; ++nb) xs.slot[(nb & 1) * G + i] = (((nb >> 1) + 1) & 1) << 63;
     xs.flag[i] = n0;
-    if (i == 0) *xs.emitted = 0;
+    if (i == 0) {
+        *xs.emitted = 0;
+        xs.start[0] = st->fired;
+        xs.start[1] = st->nulls;
+        xs.start[2] = (uint64_t)st->M;
+        xs.start[3] = (uint64_t)st->B;
+    }
 }
 // and (incremental engine) no pushed class changes pending: the launch starts
 // from histograms binned afresh.
-__global__ void k_persistent_prep(PersistScratch xs, uint32_t G, uint64_t n0, uint64_t *dh, uint64_t ndh) {
+__global__ void k_persistent_prep(PersistScratch xs, uint32_t G, uint64_t n0, const DevState *st, uint64_t *dh,
+                                  uint64_t ndh) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < G) prep_one(xs, G, n0, (uint32_t)i);
+    if (i < G) prep_one(xs, G, n0, (uint32_t)i, st);
     for (uint64_t w = i; w < ndh; w += (uint64_t)gridDim.x * blockDim.x) dh[w] = 0;
 }
 __global__ void k_persistent_prep_batch(const Replica *__restrict__ reps, uint32_t nrep, int zero_dh) {
     for (uint32_t r = blockIdx.x; r < nrep; r += gridDim.x) {
-        for (uint32_t i = threadIdx.x; i < reps[r].G; i += blockDim.x) prep_one(reps[r].xs, reps[r].G, reps[r].n0, i);
+        for (uint32_t i = threadIdx.x; i < reps[r].G; i += blockDim.x)
+            prep_one(reps[r].xs, reps[r].G, reps[r].n0, i, reps[r].g.st);
         if (zero_dh) {
             const uint64_t ndh = (uint64_t)reps[r].g.K * 16;
             for (uint64_t w = threadIdx.x; w < ndh; w += blockDim.x) reps[r].g.dh[w] = 0;
@@ -906,6 +915,7 @@ PersistScratch scratch_of(const Geom &g, int G) {
     xs.flag = g.sync + 2 * (uint64_t)G;
     xs.recp = reinterpret_cast<int64_t *>(g.sync + 3 * (uint64_t)G);
     xs.emitted = g.sync + 15 * (uint64_t)G;  // within the 16 spare words
+    xs.start = xs.emitted + 1;               // 4 more of them
     return xs;
 }
 
@@ -918,7 +928,8 @@ hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint3
     const uint64_t ndh = inc ? (uint64_t)g.K * 16 : 0;
     uint64_t blocks = ((uint64_t)grid + 255) / 256, bdh = (ndh + 255) / 256;
     blocks = blocks > bdh ? blocks : (bdh < 2048 ? bdh : 2048);
-    hipLaunchKernelGGL(k_persistent_prep, dim3((uint32_t)blocks), dim3(256), 0, stream, xs, (uint32_t)grid, n0, g.dh, ndh);
+    hipLaunchKernelGGL(k_persistent_prep, dim3((uint32_t)blocks), dim3(256), 0, stream, xs, (uint32_t)grid, n0,
+                       (const DevState *)g.st, g.dh, ndh);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     Replica R;
@@ -934,9 +945,9 @@ hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint3
     return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(block), args, 0, stream);
 }
 
-hipError_t launch_persistent_prep(const PersistScratch &xs, uint32_t G, uint64_t n0, hipStream_t stream) {
-    hipLaunchKernelGGL(k_persistent_prep, dim3((G + 255) / 256), dim3(256), 0, stream, xs, G, n0, (uint64_t *)nullptr,
-                       (uint64_t)0);
+hipError_t launch_persistent_prep(const PersistScratch &xs, uint32_t G, uint64_t n0, DevState *st, hipStream_t stream) {
+    hipLaunchKernelGGL(k_persistent_prep, dim3((G + 255) / 256), dim3(256), 0, stream, xs, G, n0, (const DevState *)st,
+                       (uint64_t *)nullptr, (uint64_t)0);
     return hipGetLastError();
 }
 

@@ -347,8 +347,9 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
     __syncthreads();
 
     DevState *st = g.st;
-    const uint64_t fired0 = st->fired, nulls0 = st->nulls;
-    const int64_t M0 = st->M, B0 = st->B;
+    const StartTotals st0 = start_totals(xs);  // the prep kernel's copy
+    const uint64_t fired0 = st0.fired, nulls0 = st0.nulls;
+    const int64_t M0 = st0.M, B0 = st0.B;
     double t = st->t;
     long long myF = 0, mydM = 0, mydB = 0;
     uint32_t rec_index = 0;
@@ -969,7 +970,7 @@ hipError_t launch_slab(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t ob
                        hipStream_t stream) {
     if (!g.sc || g.h != 16) return hipErrorInvalidValue;
     PersistScratch xs = scratch_of(g, grid);
-    hipError_t e = launch_persistent_prep(xs, (uint32_t)grid, n0, stream);
+    hipError_t e = launch_persistent_prep(xs, (uint32_t)grid, n0, g.st, stream);
     if (e != hipSuccess) return e;
     Replica R;
     R.g = g;

@@ -24,6 +24,7 @@ struct PersistScratch {
     uint64_t *flag;     // G: cycles whose flips are complete
     int64_t *recp;      // kRecBanks x G x 3: counter partials (fired, dM, dB) since launch start
     uint64_t *emitted;  // records of this launch appended so far (fixed-bound variant)
+    uint64_t *start;    // fired, nulls, M, B at launch start, copied by the prep kernel
 };
 constexpr uint64_t kScratchWordsPerWg = 2 + 1 + 3 * kRecBanks;
 
@@ -698,6 +699,23 @@ struct RowsGeometry {
 // The sync scratch of a persistent launch of G workgroups (kernels_persistent.hip),
 // and its set-up before a launch starting at cycle n0.
 PersistScratch scratch_of(const Geom &g, int G);
-hipError_t launch_persistent_prep(const PersistScratch &xs, uint32_t G, uint64_t n0, hipStream_t stream);
+hipError_t launch_persistent_prep(const PersistScratch &xs, uint32_t G, uint64_t n0, DevState *st, hipStream_t stream);
+
+// The lattice's counters at launch start.  The prep kernel copies them before
+// the launch: a workgroup folds its own totals into DevState when it leaves the
+// cycle loop, and without a device-wide R_max exchange (the fixed bound) a
+// workgroup may do so before workgroup 0 has read them.
+struct StartTotals {
+    uint64_t fired, nulls;
+    int64_t M, B;
+};
+__device__ __forceinline__ StartTotals start_totals(const PersistScratch &xs) {
+    StartTotals s;
+    s.fired = xs.start[0];
+    s.nulls = xs.start[1];
+    s.M = (int64_t)xs.start[2];
+    s.B = (int64_t)xs.start[3];
+    return s;
+}
 
 }  // namespace spkmc

@@ -69,6 +69,8 @@ static bool validate(const spkmc_params *p, std::string &why) {
     if (p->domain < 2 || (p->domain & 1)) { why = "domain edge must be even and >= 2"; return false; }
     if (p->L % p->domain) { why = "L must be a multiple of the domain edge"; return false; }
     if (p->L > 4096) { why = "L above 4096 is not supported"; return false; }
+    // octant sites and word counts are 32-bit: h^3 < 2^31
+    if (p->domain > 2048) { why = "domain edge above 2048 is not supported (octants of 2^31 sites or more)"; return false; }
     {
         const uint64_t nd = (uint64_t)(p->L / p->domain);
         const uint64_t lines = nd * nd * nd * ((p->variant & SPKMC_VARIANT_TWO_COLOURS) ? 4 : 1);

@@ -52,7 +52,9 @@ def test_struct_sizes_match_header(spkmc):
                                 dict(L=16, domain=8, init=5), dict(L=16, domain=8, engine=9),
                                 dict(L=8192, domain=32, layout="packed"),       # L above 4096
                                 dict(L=4096, domain=2),                         # 2^33 lines
-                                dict(L=2048, domain=2, variant=2)])             # 2^32 lines (two colours)
+                                dict(L=2048, domain=2, variant=2),              # 2^32 lines (two colours)
+                                dict(L=4096, domain=4096),                      # octant of 2^33 sites
+                                dict(L=4096, domain=4096, layout="packed")])
 def test_invalid_parameters(spkmc, kw):
     p = spkmc.make_params(**kw)
     assert spkmc.state_bytes(p) == 0
