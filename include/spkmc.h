@@ -260,6 +260,19 @@ size_t spkmc_batch_workspace_bytes(size_t n);
 spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
                              int32_t wg_domains, void *dev_workspace, size_t ws_bytes, spkmc_batch_info *info);
 
+/* spkmc_run_batch for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid allocation): the same launch with the same
+ * results, bit for bit, but the descriptors go into a device array of the
+ * library (one per GPU, 512 descriptors, kept until the process ends) instead
+ * of a caller's workspace.  It calls no hipMalloc or hipFree; its first call
+ * on a device resolves that device's array address.  At most 512 lattices per
+ * call (E_RANGE otherwise).  Every call on one GPU shares the array: calls
+ * whose launches can overlap on one GPU (different streams) race and must not
+ * be made; calls on one stream run in order.  Arguments and errors otherwise as
+ * for spkmc_run_batch. */
+spkmc_status spkmc_run_batch_static(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
+                                    int32_t wg_domains, spkmc_batch_info *info);
+
 /* A batch macro-step captured once into a HIP graph and replayed: the slot and
  * flag set-up, the persistent batch launch and a kernel that advances every
  * descriptor's start cycle by its cycle count, so that each replay continues

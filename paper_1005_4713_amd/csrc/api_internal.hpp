@@ -36,6 +36,11 @@ hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t 
 hipError_t upload_replicas(const Replica *host, uint32_t n, Replica *dev, hipStream_t stream);
 hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipStream_t stream);
 hipError_t capture_batch(Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipGraph_t *graph);
+// The device array of spkmc_run_batch_static on the current device (resolved
+// on the first call per device), its capacity in lattices and its bytes.
+hipError_t static_replicas(Replica **out);
+uint32_t static_replica_cap();
+size_t static_replica_bytes();
 }  // namespace spkmc
 
 struct spkmc_ctx {

@@ -46,6 +46,7 @@
 //     workgroup 0 sums them two cycles later while it waits for R_max.
 // Every wait is bounded in wall-clock time; a timeout sets DevState::error and
 // every workgroup leaves the loop.
+#include <mutex>
 #include <string>
 
 #include "persistent_common.hpp"
@@ -1025,6 +1026,40 @@ hipError_t upload_replicas(const Replica *host, uint32_t n, Replica *dev, hipStr
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// The descriptors of spkmc_run_batch_static live in this file-scope device
+// array instead of a caller's workspace, so that entry point allocates nothing.
+// Each device holds its own copy at its own address, resolved once per device
+// (with that device current); host code passes only the resolved address to
+// kernels.  Every call on a device shares the array: the descriptors are
+// written in full, in stream order, before each launch that reads them.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kStaticReplicas = 512;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticReplicas * sizeof(Replica)];
+
+uint32_t static_replica_cap() { return kStaticReplicas; }
+size_t static_replica_bytes() { return sizeof(scratch); }
+
+hipError_t static_replicas(Replica **out) {
+    static std::mutex mu;
+    static void *resolved[kMaxDevices];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!resolved[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        resolved[dev] = ptr;
+    }
+    *out = reinterpret_cast<Replica *>(resolved[dev]);
     return hipSuccess;
 }
 

@@ -613,16 +613,13 @@ struct spkmc_batch_graph {
 
 extern "C" {
 
-spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
-                             int32_t wg_domains, void *dev_workspace, size_t ws_bytes, spkmc_batch_info *info) {
-    BatchPlan bp;
-    spkmc_status st = plan_batch(ctxs, n, ncycles, obs_every, wg_domains, dev_workspace, ws_bytes, bp);
-    if (st != SPKMC_OK || bp.live.empty()) return st;
+}  // extern "C"
+
+// Upload a planned batch's descriptors to dev_reps and launch it.
+static spkmc_status launch_planned(BatchPlan &bp, Replica *dev_reps, spkmc_batch_info *info) {
     const uint32_t nl = (uint32_t)bp.live.size();
-    hipError_t e = upload_replicas(reinterpret_cast<const Replica *>(bp.host.data()), nl,
-                                   reinterpret_cast<Replica *>(dev_workspace), bp.stream);
-    if (e == hipSuccess)
-        e = launch_batch(reinterpret_cast<const Replica *>(dev_workspace), nl, bp.h, bp.P, bp.grid, bp.block, bp.stream);
+    hipError_t e = upload_replicas(reinterpret_cast<const Replica *>(bp.host.data()), nl, dev_reps, bp.stream);
+    if (e == hipSuccess) e = launch_batch(dev_reps, nl, bp.h, bp.P, bp.grid, bp.block, bp.stream);
     if (e != hipSuccess) {
         for (spkmc_ctx *c : bp.live) c->failed = true;
         return fail(nullptr, SPKMC_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
@@ -630,6 +627,31 @@ spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *n
     for (size_t i = 0; i < bp.live.size(); ++i) bp.live[i]->cycle += bp.nc[i];
     batch_info_of(bp, info);
     return SPKMC_OK;
+}
+
+extern "C" {
+
+spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
+                             int32_t wg_domains, void *dev_workspace, size_t ws_bytes, spkmc_batch_info *info) {
+    BatchPlan bp;
+    spkmc_status st = plan_batch(ctxs, n, ncycles, obs_every, wg_domains, dev_workspace, ws_bytes, bp);
+    if (st != SPKMC_OK || bp.live.empty()) return st;
+    return launch_planned(bp, reinterpret_cast<Replica *>(dev_workspace), info);
+}
+
+spkmc_status spkmc_run_batch_static(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
+                                    int32_t wg_domains, spkmc_batch_info *info) {
+    if (n > static_replica_cap())
+        return fail(nullptr, SPKMC_E_RANGE,
+                    "spkmc_run_batch_static takes at most " + std::to_string(static_replica_cap()) + " lattices");
+    Replica *dev_reps = nullptr;
+    hipError_t e = static_replicas(&dev_reps);
+    if (e != hipSuccess)
+        return fail(nullptr, SPKMC_E_DEVICE, std::string("static descriptor array: ") + hipGetErrorString(e));
+    BatchPlan bp;
+    spkmc_status st = plan_batch(ctxs, n, ncycles, obs_every, wg_domains, dev_reps, static_replica_bytes(), bp);
+    if (st != SPKMC_OK || bp.live.empty()) return st;
+    return launch_planned(bp, dev_reps, info);
 }
 
 spkmc_status spkmc_batch_graph_create(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,

@@ -73,7 +73,7 @@ SERVE_KEEP = 1
 EXPORTS = ["spkmc_state_bytes", "spkmc_init", "spkmc_run", "spkmc_observables", "spkmc_records",
            "spkmc_copy_spins", "spkmc_set_spins", "spkmc_rate_table", "spkmc_save", "spkmc_load",
            "spkmc_query", "spkmc_last_error", "spkmc_destroy", "spkmc_batch_workspace_bytes",
-           "spkmc_run_batch", "spkmc_batch_graph_create", "spkmc_batch_graph_launch", "spkmc_batch_graph_destroy",
+           "spkmc_run_batch", "spkmc_run_batch_static", "spkmc_batch_graph_create", "spkmc_batch_graph_launch", "spkmc_batch_graph_destroy",
            "spkmc_server_reserved_bytes", "spkmc_server_create", "spkmc_server_submit",
            "spkmc_server_step", "spkmc_server_poll", "spkmc_server_context", "spkmc_server_release",
            "spkmc_server_clock", "spkmc_server_last_error", "spkmc_server_destroy"]
@@ -114,6 +114,8 @@ def _load():
     lib.spkmc_destroy.argtypes = [vp]
     lib.spkmc_batch_workspace_bytes.restype = C.c_size_t
     lib.spkmc_batch_workspace_bytes.argtypes = [C.c_size_t]
+    lib.spkmc_run_batch_static.restype = C.c_int
+    lib.spkmc_run_batch_static.argtypes = [P(vp), C.c_size_t, P(C.c_uint64), C.c_uint32, C.c_int32, P(BatchInfo)]
     lib.spkmc_run_batch.restype = C.c_int
     lib.spkmc_run_batch.argtypes = [P(vp), C.c_size_t, P(C.c_uint64), C.c_uint32, C.c_int32, vp, C.c_size_t,
                                     P(BatchInfo)]
@@ -303,6 +305,23 @@ def run_batch(sims, ncycles, obs_every=0, wg_domains=0):
     info = BatchInfo()
     st = lib.spkmc_run_batch(ctxs, n, cyc, int(obs_every), int(wg_domains), C.c_void_p(ws.data_ptr()),
                              ws.numel(), C.byref(info))
+    if st != OK:
+        raise SpkmcError(st, lib.spkmc_last_error(None).decode())
+    return {f: getattr(info, f) for f, _ in BatchInfo._fields_}
+
+
+def run_batch_static(sims, ncycles, obs_every=0, wg_domains=0):
+    """run_batch without a workspace: the descriptors go into the library's own
+    device array (at most 512 lattices; no device allocation)."""
+    n = len(sims)
+    if n == 0:
+        return None
+    if isinstance(ncycles, int):
+        ncycles = [ncycles] * n
+    ctxs = (C.c_void_p * n)(*[sim.ctx.value for sim in sims])
+    cyc = (C.c_uint64 * n)(*[int(c) for c in ncycles])
+    info = BatchInfo()
+    st = lib.spkmc_run_batch_static(ctxs, n, cyc, int(obs_every), int(wg_domains), C.byref(info))
     if st != OK:
         raise SpkmcError(st, lib.spkmc_last_error(None).decode())
     return {f: getattr(info, f) for f, _ in BatchInfo._fields_}
