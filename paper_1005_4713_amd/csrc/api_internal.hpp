@@ -22,13 +22,18 @@ hipError_t launch_cycle_slab(const Geom &g, uint64_t n, hipStream_t stream);
 bool persistent_supported(const Geom &g, const spkmc_params &p, bool inc, std::string &why);
 hipError_t persistent_configure(const Geom &g, const spkmc_params &p, bool inc, int &grid, int &block,
                                 int &wg_domains);
+// prep = false skips the slot and flag set-up: allowed only when the previous
+// launch on this lattice had the same grid, ended at n0, and the launches since
+// the last set-up ran at least two cycles (they then leave the slots and flags
+// exactly as the set-up would).
 hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid,
-                             int block, int wg_domains, bool inc, hipStream_t stream);
+                             int block, int wg_domains, bool inc, bool prep, hipStream_t stream);
 uint64_t persistent_scratch_words(uint64_t K);
 // Slab engine (PACKED, octant edge 16, variant 0): support, launch shape, launch.
 bool slab_supported(const Geom &g, const spkmc_params &p, std::string &why);
 hipError_t slab_configure(const Geom &g, int &grid, int &block, int &wg_domains);
-hipError_t launch_slab(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid, hipStream_t stream);
+hipError_t launch_slab(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid, bool prep,
+                       hipStream_t stream);
 struct Replica;
 size_t replica_bytes();
 hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t *ncycles, uint32_t obs_every,
@@ -52,6 +57,11 @@ struct spkmc_ctx {
     size_t spin_off, spin_bytes;   // spin region (A + F, or int8), for save/load
     size_t rec_off;
     uint64_t cycle;                // cycles enqueued
+    // the persistent engines' sync words as the last launch left them: ready
+    // for a launch of primed_grid workgroups starting at primed_cycle when
+    // primed_span (cycles run since their last set-up) is at least 2
+    int primed_grid;
+    uint64_t primed_cycle, primed_span;
     int engine;
     int grid, block, wg_domains;
     bool failed;

@@ -165,7 +165,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         sh.abort = 0;
         sh.pend_head = sh.pend_tail = 0;
     }
-    if (tid < 8) sh.rpred[tid] = 0.0;  // no prediction yet
+    load_predictions(sh, xs);
     if (tid < 14) sh.r[tid] = g.r[tid];
     if (l < 8) sh.zbuf[row][16 + l] = 0;
     for (uint32_t i = tid; i < nvalid * 6; i += nthr) {
@@ -183,15 +183,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         if (owner != gid) atomicOr(&sh.nbr_bits[dir][owner >> 5], 1u << (owner & 31));
     }
     __syncthreads();
-    if (tid < 6) {
-        uint32_t cnt = 0;
-        for (uint32_t w = 0; w < G; ++w)
-            if ((sh.nbr_bits[tid][w >> 5] >> (w & 31)) & 1u) {
-                if (cnt < kMaxNbr) sh.nbr[tid][cnt] = w;
-                ++cnt;
-            }
-        sh.nbr_cnt[tid] = cnt;
-    }
+    list_neighbours(sh, G);
     __syncthreads();
 
     // INC: the histograms of all eight octants, from the spins at launch start
@@ -202,10 +194,10 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     }
 
     DevState *st = g.st;
-    // launch-start totals (the prep kernel's copy)
-    const StartTotals st0 = start_totals(xs);
-    const uint64_t fired0 = st0.fired, nulls0 = st0.nulls;
-    const int64_t M0 = st0.M, B0 = st0.B;
+    // launch-start totals: during a launch only the recorder writes them, at
+    // its very end, after every workgroup has finished
+    const uint64_t fired0 = st->fired, nulls0 = st->nulls;
+    const int64_t M0 = st->M, B0 = st->B;
     double t = st->t;  // every workgroup advances the same clock
     long long myF = 0, mydM = 0, mydB = 0;  // this thread's share since launch start
     uint32_t rec_index = 0;                  // records produced in this launch
@@ -633,12 +625,8 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                     dB += sh.red[2][w];
                 }
                 if (last) {
-                    // end of the launch: fold this workgroup's share into the totals
-                    atomicAdd((unsigned long long *)&st->fired, (unsigned long long)F);
-                    atomicAdd((unsigned long long *)&st->nulls,
-                              (unsigned long long)((long long)nvalid * (long long)ncycles - F));
-                    atomicAdd((unsigned long long *)&st->M, (unsigned long long)dM);
-                    atomicAdd((unsigned long long *)&st->B, (unsigned long long)dB);
+                    // end of the launch: this workgroup's totals since launch start
+                    store_final(xs, gid, F, dM, dB);
                 } else {
                     const uint32_t bank = rec_index % kRecBanks;
                     if (bound) {
@@ -723,17 +711,18 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                 emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
                 __builtin_amdgcn_wave_barrier();
             }
+            fold_final(g, xs, sh, G, tid, NL * ncycles, fired0, nulls0, M0, B0);
             if (tid == 0) {
                 st->t = t;
                 st->cycle = n_end;
                 if (obs_every && (n_end % obs_every) == 0 && g.rec_cap) {
                     spkmc_record r;
                     r.cycle = n_end;
-                    r.fired = ld64(&st->fired);
-                    r.nulls = ld64(&st->nulls);
+                    r.fired = st->fired;
+                    r.nulls = st->nulls;
                     r.t = t;
-                    r.M = (int64_t)ld64((const uint64_t *)&st->M);
-                    r.B = (int64_t)ld64((const uint64_t *)&st->B);
+                    r.M = st->M;
+                    r.B = st->B;
                     g.rec[st->rec_count % g.rec_cap] = r;
                     st->rec_count += 1;
                 }
@@ -776,32 +765,25 @@ __global__ void __launch_bounds__(BLOCK) k_persistent_batch(const Replica *__res
 }
 
 // Before a launch: slots carry the generation of no cycle of this launch yet,
-// flags the start cycle; the counters at launch start are copied.
-__device__ __forceinline__ void prep_one(const PersistScratch &xs, uint32_t G, uint64_t n0, uint32_t i,
-                                         const DevState *st) {
+// flags the start cycle.  (The end of a launch of at least two cycles leaves
+// both in exactly this state for a launch of the same shape that continues
+// where it stopped.)
+__device__ __forceinline__ void prep_one(const PersistScratch &xs, uint32_t G, uint64_t n0, uint32_t i) {
     // bank b first serves cycle nb (n0 or n0 + 1, nb & 1 == b): mark it "not yet"
     for (uint64_t nb = n0; nb < n0 + 2; ++nb) xs.slot[(nb & 1) * G + i] = (((nb >> 1) + 1) & 1) << 63;
     xs.flag[i] = n0;
-    if (i == 0) {
-        *xs.emitted = 0;
-        xs.start[0] = st->fired;
-        xs.start[1] = st->nulls;
-        xs.start[2] = (uint64_t)st->M;
-        xs.start[3] = (uint64_t)st->B;
-    }
+    if (i == 0) *xs.emitted = 0;
 }
 // and (incremental engine) no pushed class changes pending: the launch starts
 // from histograms binned afresh.
-__global__ void k_persistent_prep(PersistScratch xs, uint32_t G, uint64_t n0, const DevState *st, uint64_t *dh,
-                                  uint64_t ndh) {
+__global__ void k_persistent_prep(PersistScratch xs, uint32_t G, uint64_t n0, uint64_t *dh, uint64_t ndh) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < G) prep_one(xs, G, n0, (uint32_t)i, st);
+    if (i < G) prep_one(xs, G, n0, (uint32_t)i);
     for (uint64_t w = i; w < ndh; w += (uint64_t)gridDim.x * blockDim.x) dh[w] = 0;
 }
 __global__ void k_persistent_prep_batch(const Replica *__restrict__ reps, uint32_t nrep, int zero_dh) {
     for (uint32_t r = blockIdx.x; r < nrep; r += gridDim.x) {
-        for (uint32_t i = threadIdx.x; i < reps[r].G; i += blockDim.x)
-            prep_one(reps[r].xs, reps[r].G, reps[r].n0, i, reps[r].g.st);
+        for (uint32_t i = threadIdx.x; i < reps[r].G; i += blockDim.x) prep_one(reps[r].xs, reps[r].G, reps[r].n0, i);
         if (zero_dh) {
             const uint64_t ndh = (uint64_t)reps[r].g.K * 16;
             for (uint64_t w = threadIdx.x; w < ndh; w += blockDim.x) reps[r].g.dh[w] = 0;
@@ -915,24 +897,27 @@ PersistScratch scratch_of(const Geom &g, int G) {
     xs.slot = g.sync;
     xs.flag = g.sync + 2 * (uint64_t)G;
     xs.recp = reinterpret_cast<int64_t *>(g.sync + 3 * (uint64_t)G);
-    xs.emitted = g.sync + 15 * (uint64_t)G;  // within the 16 spare words
-    xs.start = xs.emitted + 1;               // 4 more of them
+    xs.fin = reinterpret_cast<int64_t *>(g.sync + 15 * (uint64_t)G);
+    xs.emitted = g.sync + 18 * (uint64_t)G;                  // within the 16 spare words
+    xs.rpred = reinterpret_cast<double *>(xs.emitted + 1);  // 8 more of them
     return xs;
 }
 
 hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid, int block,
-                             int wg_domains, bool inc, hipStream_t stream) {
+                             int wg_domains, bool inc, bool prep, hipStream_t stream) {
     PersistScratch xs = scratch_of(g, grid);
     const int pc = wg_domains / (block / 16), P = pc < 4 ? pc : 4;  // passes, then rounds of four passes
     void *kern = select_kernel(g.h, P, block, false, inc, g.lpd, pc / P);
     if (!kern) return hipErrorInvalidValue;
-    const uint64_t ndh = inc ? (uint64_t)g.K * 16 : 0;
-    uint64_t blocks = ((uint64_t)grid + 255) / 256, bdh = (ndh + 255) / 256;
-    blocks = blocks > bdh ? blocks : (bdh < 2048 ? bdh : 2048);
-    hipLaunchKernelGGL(k_persistent_prep, dim3((uint32_t)blocks), dim3(256), 0, stream, xs, (uint32_t)grid, n0,
-                       (const DevState *)g.st, g.dh, ndh);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (prep || inc) {  // the incremental engine clears its pushed class changes every launch
+        const uint64_t ndh = inc ? (uint64_t)g.K * 16 : 0;
+        uint64_t blocks = ((uint64_t)grid + 255) / 256, bdh = (ndh + 255) / 256;
+        blocks = blocks > bdh ? blocks : (bdh < 2048 ? bdh : 2048);
+        hipLaunchKernelGGL(k_persistent_prep, dim3((uint32_t)blocks), dim3(256), 0, stream, xs, (uint32_t)grid, n0,
+                           g.dh, ndh);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     Replica R;
     R.g = g;
     R.xs = xs;
@@ -946,9 +931,9 @@ hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint3
     return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(block), args, 0, stream);
 }
 
-hipError_t launch_persistent_prep(const PersistScratch &xs, uint32_t G, uint64_t n0, DevState *st, hipStream_t stream) {
-    hipLaunchKernelGGL(k_persistent_prep, dim3((G + 255) / 256), dim3(256), 0, stream, xs, G, n0, (const DevState *)st,
-                       (uint64_t *)nullptr, (uint64_t)0);
+hipError_t launch_persistent_prep(const PersistScratch &xs, uint32_t G, uint64_t n0, hipStream_t stream) {
+    hipLaunchKernelGGL(k_persistent_prep, dim3((G + 255) / 256), dim3(256), 0, stream, xs, G, n0, (uint64_t *)nullptr,
+                       (uint64_t)0);
     return hipGetLastError();
 }
 

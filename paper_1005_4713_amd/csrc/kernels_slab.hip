@@ -308,7 +308,7 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
         sh.abort = 0;
         sh.pend_head = sh.pend_tail = 0;
     }
-    if (tid < 8) sh.rpred[tid] = 0.0;
+    load_predictions(sh, xs);
     if (tid < 14) sh.r[tid] = g.r[tid];
     if (l < 8) sh.zbuf[row][16 + l] = 0;
     for (uint32_t i = tid; i < nvalid * 6; i += nthr) {
@@ -327,15 +327,7 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
         if (owner != gid) atomicOr(&sh.nbr_bits[dir][owner >> 5], 1u << (owner & 31));
     }
     __syncthreads();
-    if (tid < 6) {
-        uint32_t cnt = 0;
-        for (uint32_t w = 0; w < G; ++w)
-            if ((sh.nbr_bits[tid][w >> 5] >> (w & 31)) & 1u) {
-                if (cnt < kMaxNbr) sh.nbr[tid][cnt] = w;
-                ++cnt;
-            }
-        sh.nbr_cnt[tid] = cnt;
-    }
+    list_neighbours(sh, G);
     __syncthreads();
 
     // slab counts of all eight octants from the spins at launch start; they are
@@ -347,9 +339,10 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
     __syncthreads();
 
     DevState *st = g.st;
-    const StartTotals st0 = start_totals(xs);  // the prep kernel's copy
-    const uint64_t fired0 = st0.fired, nulls0 = st0.nulls;
-    const int64_t M0 = st0.M, B0 = st0.B;
+    // launch-start totals: during a launch only the recorder writes them, at
+    // its very end, after every workgroup has finished
+    const uint64_t fired0 = st->fired, nulls0 = st->nulls;
+    const int64_t M0 = st->M, B0 = st->B;
     double t = st->t;
     long long myF = 0, mydM = 0, mydB = 0;
     uint32_t rec_index = 0;
@@ -643,11 +636,8 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
                     dB += sh.red[2][w];
                 }
                 if (last) {
-                    atomicAdd((unsigned long long *)&st->fired, (unsigned long long)F);
-                    atomicAdd((unsigned long long *)&st->nulls,
-                              (unsigned long long)((long long)nvalid * (long long)ncycles - F));
-                    atomicAdd((unsigned long long *)&st->M, (unsigned long long)dM);
-                    atomicAdd((unsigned long long *)&st->B, (unsigned long long)dB);
+                    // end of the launch: this workgroup's totals since launch start
+                    store_final(xs, gid, F, dM, dB);
                 } else {
                     const uint32_t bankr = rec_index % kRecBanks;
                     int64_t *rp = xs.recp + (uint64_t)bankr * G * 3;
@@ -692,17 +682,18 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
                 emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
                 __builtin_amdgcn_wave_barrier();
             }
+            fold_final(g, xs, sh, G, tid, (uint64_t)g.K * ncycles, fired0, nulls0, M0, B0);
             if (tid == 0) {
                 st->t = t;
                 st->cycle = n_end;
                 if (obs_every && (n_end % obs_every) == 0 && g.rec_cap) {
                     spkmc_record r;
                     r.cycle = n_end;
-                    r.fired = ld64(&st->fired);
-                    r.nulls = ld64(&st->nulls);
+                    r.fired = st->fired;
+                    r.nulls = st->nulls;
                     r.t = t;
-                    r.M = (int64_t)ld64((const uint64_t *)&st->M);
-                    r.B = (int64_t)ld64((const uint64_t *)&st->B);
+                    r.M = st->M;
+                    r.B = st->B;
                     g.rec[st->rec_count % g.rec_cap] = r;
                     st->rec_count += 1;
                 }
@@ -966,12 +957,14 @@ hipError_t slab_configure(const Geom &g, int &grid, int &block, int &wg_domains)
     return hipSuccess;
 }
 
-hipError_t launch_slab(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid,
+hipError_t launch_slab(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t obs_every, int grid, bool prep,
                        hipStream_t stream) {
     if (!g.sc || g.h != 16) return hipErrorInvalidValue;
     PersistScratch xs = scratch_of(g, grid);
-    hipError_t e = launch_persistent_prep(xs, (uint32_t)grid, n0, g.st, stream);
-    if (e != hipSuccess) return e;
+    if (prep) {
+        hipError_t e = launch_persistent_prep(xs, (uint32_t)grid, n0, stream);
+        if (e != hipSuccess) return e;
+    }
     Replica R;
     R.g = g;
     R.xs = xs;

@@ -23,10 +23,11 @@ struct PersistScratch {
     uint64_t *slot;     // 2 x G: R_max of each workgroup, generation bit 63
     uint64_t *flag;     // G: cycles whose flips are complete
     int64_t *recp;      // kRecBanks x G x 3: counter partials (fired, dM, dB) since launch start
-    uint64_t *emitted;  // records of this launch appended so far (fixed-bound variant)
-    uint64_t *start;    // fired, nulls, M, B at launch start, copied by the prep kernel
+    int64_t *fin;       // G x 3: each workgroup's totals (fired, dM, dB) at the end of the launch
+    uint64_t *emitted;  // records of this launch appended so far (fixed-bound variant); 0 between launches
+    double *rpred;      // 8: the last R_max of each colour, the next launch's first predictions
 };
-constexpr uint64_t kScratchWordsPerWg = 2 + 1 + 3 * kRecBanks;
+constexpr uint64_t kScratchWordsPerWg = 2 + 1 + 3 * kRecBanks + 3;
 
 // One lattice of a persistent launch: its geometry and buffers, its sync
 // scratch, the cycles to run, and its range of workgroups in the launch.
@@ -699,23 +700,76 @@ struct RowsGeometry {
 // The sync scratch of a persistent launch of G workgroups (kernels_persistent.hip),
 // and its set-up before a launch starting at cycle n0.
 PersistScratch scratch_of(const Geom &g, int G);
-hipError_t launch_persistent_prep(const PersistScratch &xs, uint32_t G, uint64_t n0, DevState *st, hipStream_t stream);
+hipError_t launch_persistent_prep(const PersistScratch &xs, uint32_t G, uint64_t n0, hipStream_t stream);
 
-// The lattice's counters at launch start.  The prep kernel copies them before
-// the launch: a workgroup folds its own totals into DevState when it leaves the
-// cycle loop, and without a device-wide R_max exchange (the fixed bound) a
-// workgroup may do so before workgroup 0 has read them.
-struct StartTotals {
-    uint64_t fired, nulls;
-    int64_t M, B;
-};
-__device__ __forceinline__ StartTotals start_totals(const PersistScratch &xs) {
-    StartTotals s;
-    s.fired = xs.start[0];
-    s.nulls = xs.start[1];
-    s.M = (int64_t)xs.start[2];
-    s.B = (int64_t)xs.start[3];
-    return s;
+// The neighbour workgroups of this workgroup per direction, from the bitmap
+// sh.nbr_bits (one thread per direction, a word of the bitmap at a time).
+template <class SH>
+__device__ __forceinline__ void list_neighbours(SH &sh, uint32_t G) {
+    const int d = threadIdx.x;
+    if (d < 6) {
+        uint32_t cnt = 0;
+        for (uint32_t wd = 0; wd < (G + 31) / 32; ++wd) {
+            uint32_t bits = sh.nbr_bits[d][wd];
+            while (bits) {
+                const uint32_t w = wd * 32 + (uint32_t)__builtin_ctz(bits);
+                bits &= bits - 1;
+                if (cnt < kMaxNbr) sh.nbr[d][cnt] = w;
+                ++cnt;
+            }
+        }
+        sh.nbr_cnt[d] = cnt;
+    }
+}
+
+// The first predictions of a launch: the last R_max of each colour left by the
+// previous launch of the lattice (0 = none; a prediction only decides which
+// selection is tried first, never the outcome).
+template <class SH>
+__device__ __forceinline__ void load_predictions(SH &sh, const PersistScratch &xs) {
+    const int c = threadIdx.x;
+    if (c < 8) {
+        const double v = xs.rpred[c];
+        sh.rpred[c] = (v > 0.0 && v < 1.0e300) ? v : 0.0;
+    }
+}
+
+// End of a launch in every workgroup: its totals since launch start into its
+// own words (read by the recorder once every flag has reached the last cycle).
+__device__ __forceinline__ void store_final(const PersistScratch &xs, uint32_t gid, long long F, long long dM,
+                                            long long dB) {
+    st64(reinterpret_cast<uint64_t *>(&xs.fin[3 * gid]), (uint64_t)F);
+    st64(reinterpret_cast<uint64_t *>(&xs.fin[3 * gid + 1]), (uint64_t)dM);
+    st64(reinterpret_cast<uint64_t *>(&xs.fin[3 * gid + 2]), (uint64_t)dB);
+}
+
+// The recorder (one wavefront) after every workgroup has finished: the totals
+// of the launch folded into the lattice's counters (NLc = frequency lines times
+// cycles of the launch), the predictions kept for the next launch, and the
+// fixed-bound record counter reset.
+template <class SH>
+__device__ __forceinline__ void fold_final(const Geom &g, const PersistScratch &xs, SH &sh, uint32_t G, int lane,
+                                           uint64_t NLc, uint64_t fired0, uint64_t nulls0, int64_t M0, int64_t B0) {
+    long long F = 0, dM = 0, dB = 0;
+    for (uint32_t w = (uint32_t)lane; w < G; w += 64) {
+        F += (long long)ld64(reinterpret_cast<const uint64_t *>(&xs.fin[3 * w]));
+        dM += (long long)ld64(reinterpret_cast<const uint64_t *>(&xs.fin[3 * w + 1]));
+        dB += (long long)ld64(reinterpret_cast<const uint64_t *>(&xs.fin[3 * w + 2]));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        F += __shfl_xor(F, o);
+        dM += __shfl_xor(dM, o);
+        dB += __shfl_xor(dB, o);
+    }
+    if (lane < 8) xs.rpred[lane] = sh.rpred[lane];
+    if (lane == 0) {
+        DevState *st = g.st;
+        st->fired = fired0 + (uint64_t)F;
+        st->nulls = nulls0 + NLc - (uint64_t)F;
+        st->M = M0 + dM;
+        st->B = B0 + dB;
+        *xs.emitted = 0;
+    }
 }
 
 }  // namespace spkmc

@@ -167,6 +167,7 @@ spkmc_status spkmc_init(const spkmc_params *p, void *dev_buf, size_t dev_bytes, 
     *out = c;
     c->failed = false;
     c->cycle = 0;
+    c->primed_grid = 0;
     std::string why;
     if (!validate(p, why)) return fail(c, SPKMC_E_INVAL, why);
     c->p = *p;
@@ -285,15 +286,23 @@ spkmc_status spkmc_run(spkmc_ctx *c, uint64_t ncycles, uint32_t obs_every) {
     if (c->failed || !c->dev) return fail(c, SPKMC_E_STATE, "context is in a failed state");
     if (ncycles == 0) return SPKMC_OK;
     hipError_t e = hipSuccess;
-    if (c->engine == SPKMC_ENGINE_SLAB) {
-        e = launch_slab(c->g, c->cycle, ncycles, obs_every, c->grid, c->stream);
-        if (e != hipSuccess) return hip_fail(c, e, "slab kernel launch");
+    if (c->engine != SPKMC_ENGINE_CYCLE) {
+        // the set-up of the sync words is needed unless the previous launch left
+        // them ready for this one
+        const bool primed = c->primed_grid == c->grid && c->primed_cycle == c->cycle && c->primed_span >= 2;
+        if (c->engine == SPKMC_ENGINE_SLAB)
+            e = launch_slab(c->g, c->cycle, ncycles, obs_every, c->grid, !primed, c->stream);
+        else
+            e = launch_persistent(c->g, c->cycle, ncycles, obs_every, c->grid, c->block, c->wg_domains,
+                                  c->engine == SPKMC_ENGINE_INCREMENTAL, !primed, c->stream);
+        if (e != hipSuccess) {
+            c->primed_grid = 0;
+            return hip_fail(c, e, c->engine == SPKMC_ENGINE_SLAB ? "slab kernel launch" : "persistent kernel launch");
+        }
+        c->primed_span = (primed ? c->primed_span : 0) + ncycles;
+        c->primed_grid = c->grid;
         c->cycle += ncycles;
-    } else if (c->engine != SPKMC_ENGINE_CYCLE) {
-        e = launch_persistent(c->g, c->cycle, ncycles, obs_every, c->grid, c->block, c->wg_domains,
-                              c->engine == SPKMC_ENGINE_INCREMENTAL, c->stream);
-        if (e != hipSuccess) return hip_fail(c, e, "persistent kernel launch");
-        c->cycle += ncycles;
+        c->primed_cycle = c->cycle;
     } else {
         // PACKED lattices with octant edge 16 run the slab kernels, whose counts
         // are binned afresh at the start of every run
@@ -416,6 +425,7 @@ static void host_observables(const int8_t *s, int L, int64_t &M, int64_t &B) {
 }
 
 spkmc_status spkmc_set_spins(spkmc_ctx *c, const int8_t *host, size_t n) {
+    if (c) c->primed_grid = 0;
     if (!c) return fail(nullptr, SPKMC_E_INVAL, "ctx is NULL");
     if (!host) return fail(c, SPKMC_E_INVAL, "host is NULL");
     if (c->failed) return fail(c, SPKMC_E_STATE, "context is in a failed state");
@@ -477,6 +487,7 @@ spkmc_status spkmc_save(spkmc_ctx *c, void *host, size_t cap, size_t *n) {
 }
 
 spkmc_status spkmc_load(spkmc_ctx *c, const void *host, size_t n) {
+    if (c) c->primed_grid = 0;
     if (!c) return fail(nullptr, SPKMC_E_INVAL, "ctx is NULL");
     if (!host) return fail(c, SPKMC_E_INVAL, "host is NULL");
     if (c->failed) return fail(c, SPKMC_E_STATE, "context is in a failed state");
@@ -624,7 +635,10 @@ static spkmc_status launch_planned(BatchPlan &bp, Replica *dev_reps, spkmc_batch
         for (spkmc_ctx *c : bp.live) c->failed = true;
         return fail(nullptr, SPKMC_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     }
-    for (size_t i = 0; i < bp.live.size(); ++i) bp.live[i]->cycle += bp.nc[i];
+    for (size_t i = 0; i < bp.live.size(); ++i) {
+        bp.live[i]->cycle += bp.nc[i];
+        bp.live[i]->primed_grid = 0;  // a batch lays out the sync words for its own grid
+    }
     batch_info_of(bp, info);
     return SPKMC_OK;
 }
@@ -671,7 +685,10 @@ spkmc_status spkmc_batch_graph_create(spkmc_ctx *const *ctxs, size_t n, const ui
     gr->members = bp.live;
     gr->nc = bp.nc;
     gr->stream = bp.stream;
-    for (spkmc_ctx *c : bp.live) gr->expect.push_back(c->cycle);
+    for (spkmc_ctx *c : bp.live) {
+        gr->expect.push_back(c->cycle);
+        c->primed_grid = 0;
+    }
     e = capture_batch(dev_reps, nl, bp.h, bp.P, bp.grid, bp.block, &gr->graph);
     if (e == hipSuccess) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
