@@ -18,3 +18,14 @@ def paper_constants():
     import json
     with open(os.path.join(ROOT, "tests", "golden", "paper_constants.json")) as f:
         return json.load(f)
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _oracle_threads():
+    """The oracle's per-domain loops on up to 16 host threads (the trajectory is
+    bit-identical for every thread count; only the full-size comparisons need
+    the speed)."""
+    import oracle
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    yield
+    oracle.set_threads(1)

@@ -1,24 +1,36 @@
-"""The stochastic bias of the sublattice method (Sec. 4, eqs. 6-7), measured
-on the GPU: magnetisation relaxation from all +1 at the critical temperature
-of a 2^18-spin lattice (L = 64), spkMC with two colours (the configuration of
-the paper's own bias runs) at 32, 256 and 2048 parallel processes against
-the mean of serial BKL runs of the oracle.
+"""The stochastic bias of the sublattice method (Sec. 4, eqs. 6-7, Figs. 2-4),
+measured on the GPU: magnetisation relaxation from all +1 at the critical
+temperature on 2^18 spins (L = 64) and 2^21 spins (L = 128), spkMC against the
+mean of serial BKL runs of the oracle.
 
 The number of parallel processes is the number of subcells per colour: with
-octants of edge h = d / 2 it is 4 (L / d)^3.  Time is in units of 1 / lambda
-(lambda = 1); the paper's own time axis cannot be mapped onto these units, so
-the window is chosen here (0.1 <= t <= 4) rather than copied.
+two colours (the paper's own bias runs) a domain of edge d holds four subcells
+of each colour (octants of edge d / 2), so 4 (L / d)^3 processes; with the
+eight-colour contract, (L / d)^3.  The paper finds the parallel runs
+statistically equivalent to the serial ones over the whole window up to 32
+processes at 2^18 spins and about 256 at 2^21, i.e. 4096 spins per subcell,
+and an early-time bias with smaller subcells that shrinks as time goes on.
 
-Also run: the eight-colour contract on the persistent engine.
+Time is in units of 1 / lambda (lambda = 1).  The paper's time axis cannot be
+mapped onto these units (from all +1 at T_c the per-site rate is 0.065), so
+the window 0.1 <= t <= 4 (the serial mean m falls from 0.99 to 0.74) is
+chosen here rather than copied.
 
-Claim checked (Fig. 4): the time-integrated bias over the window is smaller
-than 3 sigma_b, sigma_b^2 = sigma_p^2 + sigma_s^2 (standard errors of the
-parallel and serial means).  The per-time bias of Fig. 3 and the table of
-Fig. 4 are written to bias_study.json in the folder SPKMC_RESULTS_DIR names, if set.
+Claims checked where the paper makes them (4096 spins per subcell: two colours
+with d = 32 at both sizes, and the eight-colour contract with d = 32):
+  * per time: |b(t)| < 3 sigma_b(t) with b(t) = <m_p(t)> - <m_s(t)> and
+    sigma_b^2 = sigma_p^2 + sigma_s^2 (the standard errors of the two means,
+    eq. 7), at 14 log-spaced times; at most one of the 14 may exceed it (if
+    the two were equivalent, two or more would do so with probability 0.1%);
+  * time-integrated: the bias of the window average is below 3 sigma_b.
+Smaller subcells (more processes) are measured and reported, with only the
+time-integrated bias asserted.  The per-time table (Figs. 3-4) is written to
+bias_study.json in the folder SPKMC_RESULTS_DIR names, if set.
 """
 import json
 import math
 import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -28,10 +40,9 @@ import oracle
 pytestmark = pytest.mark.gpu
 
 TC = 1.0 / 0.2216546
-L = 64
 GRID = np.geomspace(0.1, 4.0, 14)
-SERIAL_RUNS = 16
-PARALLEL_RUNS = 10
+SERIAL_RUNS = 24
+PARALLEL_RUNS = 20
 
 
 @pytest.fixture(scope="module")
@@ -43,25 +54,25 @@ def spkmc():
     return mod
 
 
-def _on_grid(records, grid):
+def _on_grid(records, grid, N):
     """m at each grid time: the state after the last cycle whose clock <= t."""
     t = np.array([r[3] for r in records])
     M = np.array([r[4] for r in records], dtype=np.float64)
     idx = np.searchsorted(t, grid, side="right") - 1
     assert np.all(idx >= 0)
-    return M[idx] / L ** 3
+    return M[idx] / N
 
 
-def _parallel_curve(spkmc, d, seed, variant, engine):
+def _parallel_curve(spkmc, L, d, seed, variant, engine):
     sim = spkmc.Sim(L, d, layout="packed", engine=engine, variant=variant, T=TC, init="up", seed=seed,
-                    record_cap=1 << 18)
+                    record_cap=1 << 16)
     # one record per cycle; run until the clock passes the window
     chunk = 512
     while sim.state()[3] <= GRID[-1]:
         sim.run(chunk, obs_every=1)
     recs = sim.records()
     assert recs[0][0] == 1 and recs[-1][0] == len(recs)  # the ring kept every cycle
-    return _on_grid([(0, 0, 0, 0.0, L ** 3, 0)] + recs, GRID)
+    return _on_grid([(0, 0, 0, 0.0, L ** 3, 0)] + recs, GRID, L ** 3)
 
 
 def _integrated(curves):
@@ -69,40 +80,62 @@ def _integrated(curves):
     return vals.mean(), vals.std(ddof=1) / math.sqrt(len(vals))
 
 
-@pytest.fixture(scope="module")
-def serial():
-    print("bias study: serial BKL reference", flush=True)
-    curves = []
-    for r in range(SERIAL_RUNS):
-        M, _ = oracle.Bkl(L=L, T=TC, init=1, seed=5000 + r).run_grid(GRID)
-        assert len(M) == len(GRID)
-        curves.append(M / L ** 3)
-    return np.array(curves)
+_SERIAL = {}
+
+
+def _serial(L):
+    if L not in _SERIAL:
+        print("bias study: serial BKL reference, L =", L, flush=True)
+
+        def one(r):
+            M, _ = oracle.Bkl(L=L, T=TC, init=1, seed=5000 + 100 * L + r).run_grid(GRID)
+            assert len(M) == len(GRID)
+            return M / L ** 3
+
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            _SERIAL[L] = np.array(list(ex.map(one, range(SERIAL_RUNS))))
+    return _SERIAL[L]
 
 
 _TABLE = []
 
+# (L, variant, engine, d, claimed): claimed = the paper's equivalence regime
+CASES = [(64, "two_colours", "persistent", 32, True), (64, "two_colours", "persistent", 16, False),
+         (64, "two_colours", "cycle", 8, False), (64, "", "persistent", 32, True),
+         (64, "", "persistent", 16, False),
+         (128, "two_colours", "persistent", 32, True), (128, "two_colours", "persistent", 16, False),
+         (128, "two_colours", "cycle", 8, False), (128, "", "persistent", 32, True)]
 
-@pytest.mark.parametrize("variant,engine,d", [("two_colours", "persistent", 32), ("two_colours", "persistent", 16),
-                                             ("two_colours", "cycle", 8),
-                                             ("", "persistent", 32), ("", "persistent", 16)])
-def test_bias_within_serial_deviation(spkmc, serial, variant, engine, d):
-    print("bias study:", variant or "eight colours", engine, "d =", d, flush=True)
+
+@pytest.mark.parametrize("L,variant,engine,d,claimed", CASES,
+                         ids=[f"L{c[0]}_{c[1] or 'eight'}_d{c[3]}" for c in CASES])
+def test_bias_within_serial_deviation(spkmc, L, variant, engine, d, claimed):
+    print("bias study: L =", L, variant or "eight colours", engine, "d =", d, flush=True)
+    serial = _serial(L)
     ms, ss = _integrated(serial)
-    par = np.array([_parallel_curve(spkmc, d, 7000 + 100 * d + r, variant, engine) for r in range(PARALLEL_RUNS)])
+    par = np.array([_parallel_curve(spkmc, L, d, 7000 + 100 * d + 10000 * L + r, variant, engine)
+                    for r in range(PARALLEL_RUNS)])
     mp, sp = _integrated(par)
     sigma_b = math.sqrt(sp ** 2 + ss ** 2)
+    bias_t = par.mean(axis=0) - serial.mean(axis=0)
+    sigma_bt = np.sqrt(par.var(axis=0, ddof=1) / PARALLEL_RUNS + serial.var(axis=0, ddof=1) / SERIAL_RUNS)
+    z_t = bias_t / sigma_bt
     colours = 2 if variant else 8
     subcells = 8 * (L // d) ** 3
-    _TABLE.append({"colours": colours, "engine": engine, "domain": d, "processes": subcells // colours,
-                   "sites_per_subcell": (d // 2) ** 3, "integrated_bias": mp - ms, "sigma_b": sigma_b,
-                   "relative_bias": (mp - ms) / ms,
-                   "bias_t": (par.mean(axis=0) - serial.mean(axis=0)).tolist(),
+    _TABLE.append({"L": L, "colours": colours, "engine": engine, "domain": d, "processes": subcells // colours,
+                   "sites_per_subcell": (d // 2) ** 3, "claimed_equivalent": claimed,
+                   "integrated_bias": mp - ms, "sigma_b": sigma_b, "relative_bias": (mp - ms) / ms,
+                   "bias_t": bias_t.tolist(), "sigma_b_t": sigma_bt.tolist(), "z_t": z_t.tolist(),
                    "sigma_s_t": serial.std(axis=0, ddof=1).tolist()})
     out = os.environ.get("SPKMC_RESULTS_DIR", "")
     if out and os.path.isdir(out):
         with open(os.path.join(out, "bias_study.json"), "w") as f:
-            json.dump({"L": L, "T": TC, "grid": GRID.tolist(), "serial_runs": SERIAL_RUNS,
-                       "parallel_runs": PARALLEL_RUNS, "serial_mean_t": serial.mean(axis=0).tolist(),
-                       "serial_integrated": ms, "cases": _TABLE}, f, indent=1)
-    assert abs(mp - ms) < 3 * sigma_b, (variant, d, mp, ms, sigma_b)
+            json.dump({"T": TC, "grid": GRID.tolist(), "serial_runs": SERIAL_RUNS,
+                       "parallel_runs": PARALLEL_RUNS,
+                       "serial_mean_t": {str(k): v.mean(axis=0).tolist() for k, v in _SERIAL.items()},
+                       "cases": _TABLE}, f, indent=1)
+    print(f"  integrated bias {mp - ms:+.2e} sigma_b {sigma_b:.2e}; per-time z {np.round(z_t, 1).tolist()}",
+          flush=True)
+    assert abs(mp - ms) < 3 * sigma_b, (L, variant, d, mp, ms, sigma_b)
+    if claimed:
+        assert int(np.sum(np.abs(z_t) >= 3.0)) <= 1, (L, variant, d, z_t)

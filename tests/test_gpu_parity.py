@@ -92,18 +92,22 @@ def test_trajectory_parity_variants(spkmc, L, d, layout, kw):
 
 
 def test_medium_l128(spkmc):
-    """L = 128 (2^21 sites), d = 8, int8: 2000 of the 10^4 cycles, records every
-    10 cycles, spins at the end."""
+    """L = 128 (2^21 sites), d = 8, int8, random start: the whole run of 10^4
+    cycles, a record every 10 cycles (in two launches of 5000), every spin
+    compared at the end of each."""
     w = workloads.MEDIUM_L128
     _print_case(**w)
-    gpu, orc = _pair(spkmc, w["L"], w["domain"], layout=w["layout"], T=w["T"], seed=w["seed"])
-    gpu.run(2000, obs_every=10)
-    recs_o = orc.run(2000, obs_every=10)
-    recs_g = gpu.records(200)
-    assert len(recs_g) == 200
-    for g, o in zip(recs_g, recs_o):
-        _same_record(g, o)
-    assert np.array_equal(gpu.spins(), orc.spins())
+    gpu, orc = _pair(spkmc, w["L"], w["domain"], layout=w["layout"], T=w["T"], seed=w["seed"], record_cap=1000)
+    for half in range(2):
+        gpu.run(5000, obs_every=10)
+        recs_o = orc.run(5000, obs_every=10)
+        recs_g = gpu.records(500)
+        assert len(recs_g) == len(recs_o) == 500
+        for g, o in zip(recs_g, recs_o):
+            _same_record(g, o)
+        assert np.array_equal(gpu.spins(), orc.spins())
+        print("  half", half, "equal, state", recs_g[-1], flush=True)
+    assert gpu.state()[0] == w["cycles"]
 
 
 def test_set_spins_then_run(spkmc):

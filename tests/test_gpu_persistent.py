@@ -119,37 +119,50 @@ def _l512_sweep():
 
 
 @pytest.mark.parametrize("w", _l512_sweep(), ids=lambda w: w["name"])
-def test_large_l512_first_cycles(spkmc, w):
+def test_large_l512_vs_oracle(spkmc, w):
     """L = 512 (2^27 sites), d = 16, every configuration of the sweep (three
-    temperatures around T_c, both rate families, both starts): the first
-    cycles against the oracle."""
+    temperatures around T_c, both rate families, both starts): the first 20
+    cycles against the oracle in launches of 1, 2 and 17 cycles, a record every
+    cycle, every spin compared at the end."""
     print("case", w["name"], flush=True)
     gpu = spkmc.Sim(w["L"], w["domain"], layout="packed", engine="auto", T=w["T"], rates=w["rates"], init=w["init"],
-                    seed=w["seed"], record_cap=16)
+                    seed=w["seed"], record_cap=32)
     orc = _orc(w["L"], w["domain"], T=w["T"], seed=w["seed"], rates=w["rates"], init=w["init"])
     _same(gpu.state(), orc.state())
-    for n in (1, 2):
+    for n in (1, 2, 17):
         gpu.run(n, obs_every=1)
         ro = orc.run(n, obs_every=1)
-        for g_, o_ in zip(gpu.records(n), ro):
+        rg = gpu.records(n)
+        assert len(rg) == len(ro) == n
+        for g_, o_ in zip(rg, ro):
             _same(g_, o_)
     assert np.array_equal(gpu.spins(), orc.spins())
 
 
-def test_headline_l1024_first_cycles(spkmc):
-    """L = 1024 (2^30 sites), d = 32, T = 4.5115, seed 42, in the launch shape the
-    benchmark uses: two cycles against the oracle, every spin compared."""
-    print("case L1024 d32", flush=True)
+def test_headline_l1024_vs_oracle(spkmc):
+    """L = 1024 (2^30 sites), d = 32, T = 4.5115, seed 42, in the launch shape
+    the benchmark uses (256 workgroups of 128 domains; a short warm-up launch,
+    then a longer one): 55 cycles against the oracle, a record every cycle,
+    every spin compared at the end.  Past the first cycles the selection runs
+    on a predicted R_max that is right for almost every row, so the steady-state
+    path (prediction kept) meets the oracle here."""
+    print("case L1024 d32, 5 + 50 cycles", flush=True)
     from paper_1005_4713_amd import workloads
     w = workloads.HEADLINE_L1024
-    gpu = spkmc.Sim(w["L"], w["domain"], layout="packed", engine="auto", T=w["T"], seed=w["seed"], record_cap=16)
-    assert gpu.info()["engine"] == spkmc.ENGINES["persistent"]
+    gpu = spkmc.Sim(w["L"], w["domain"], layout="packed", engine="auto", T=w["T"], seed=w["seed"], record_cap=64)
+    info = gpu.info()
+    assert info["engine"] == spkmc.ENGINES["persistent"]
+    assert (info["grid"], info["block"], info["wg_domains"]) == (256, 512, 128)
     orc = _orc(w["L"], w["domain"], T=w["T"], seed=w["seed"])
     _same(gpu.state(), orc.state())
-    gpu.run(2, obs_every=1)
-    ro = orc.run(2, obs_every=1)
-    for g_, o_ in zip(gpu.records(2), ro):
-        _same(g_, o_)
+    for n in (5, 50):
+        gpu.run(n, obs_every=1)
+        ro = orc.run(n, obs_every=1)
+        rg = gpu.records(n)
+        assert len(rg) == len(ro) == n
+        for g_, o_ in zip(rg, ro):
+            _same(g_, o_)
+        print("  ", n, "cycles equal, state", rg[-1], flush=True)
     assert np.array_equal(gpu.spins(), orc.spins())
 
 

@@ -62,6 +62,40 @@ def test_served_equals_solo(spkmc):
     srv.close()
 
 
+def test_served_requests_vs_oracle(spkmc):
+    """Requests served in the mix (admitted while others run, advanced in shared
+    batch launches or alone) against the CPU oracle directly: the record of
+    every observation cycle, the final state and every spin.  The three cover a
+    batched octant edge 8, a batched octant edge 16 and an int8 lattice that
+    runs alone."""
+    import oracle
+    print("serve: mix, three requests checked against the oracle", flush=True)
+    srv = spkmc.Server(64 << 20, macro_cycles=40, max_live=8, inflight=2)
+    ids = []
+    for i, (L, d, lay, T, H, seed, n, obs) in enumerate(MIX):
+        ids.append(srv.submit(L, d, n, obs_every=obs, keep=True, layout=lay, T=T, H=H, seed=seed, record_cap=64))
+        if i % 2 == 1:
+            srv.step()
+    st = srv.drain()
+    assert st["done"] == len(MIX) and st["failed"] == 0
+    for k in (2, 4, 6):
+        L, d, lay, T, H, seed, n, obs = MIX[k]
+        orc = oracle.Sim(L=L, d=d, T=T, H=H, seed=seed)
+        ro = orc.run(n, obs_every=obs)
+        v = srv.lattice(ids[k], L, record_cap=64)
+        rg = v.records()
+        assert len(rg) == len(ro) == n // obs, (L, d, lay)
+        for g, o in zip(rg, ro):
+            assert g[:3] == o[:3] and g[4:] == o[4:], (L, d, lay, g, o)
+            assert abs(g[3] - o[3]) <= 1e-12 * abs(o[3]), (g, o)
+        so = orc.state()
+        sg = srv.poll(ids[k])["state_tuple"]
+        assert sg[:3] == so[:3] and sg[4:] == so[4:] and abs(sg[3] - so[3]) <= 1e-12 * abs(so[3])
+        assert np.array_equal(v.spins(), orc.spins()), (L, d, lay)
+        srv.release(ids[k])
+    srv.close()
+
+
 def test_admission_by_footprint(spkmc):
     print("serve: admission under a pool that holds two lattices", flush=True)
     one = spkmc.state_bytes(spkmc.make_params(64, 16))

@@ -287,6 +287,7 @@ def test_thread_count_independence(colours, scope):
     """The opt-in parallel-for over domains gives the single-threaded
     trajectory bit for bit (records and final spins)."""
     out = []
+    before = oracle.get_threads()
     for nt in (1, 4):
         oracle.set_threads(nt)
         try:
@@ -295,7 +296,7 @@ def test_thread_count_independence(colours, scope):
             assert sim.check_failures() == 0
             out.append((recs, sim.spins()))
         finally:
-            oracle.set_threads(1)
+            oracle.set_threads(before)
     assert out[0][0] == out[1][0]
     assert np.array_equal(out[0][1], out[1][1])
 
