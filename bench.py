@@ -10,7 +10,10 @@ Prints one JSON line: spin-flip events per second of simulated dynamics with
 the lattice resident in HBM, the roofline of the dominant kernel (algorithmic
 bytes per cycle from the method: every domain reads its active octant and its
 1-site halo at one bit per site and writes one flip, K ((h^3 + 6 h^2)/8 + 8)
-bytes), and the CPU oracle timed on a bounded sample of the same workload.
+bytes), the batched and served forms on the replica mix (throughput, p50/p99
+latency of the served requests, each against the plain path and the plain
+1024^3 kernel), and the CPU oracle timed on a bounded sample of the same
+workload (on all host threads, and on one).
 """
 import argparse
 import json
@@ -44,6 +47,7 @@ def parse():
     ap.add_argument("--wg-domains", type=int, default=0)
     ap.add_argument("--obs-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mix", action="store_true", help="headline: skip the batched and served replica-mix legs")
     ap.add_argument("--cpu-cycles", type=int, default=0, help="oracle cycles for the CPU baseline (0 = auto)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="instead of the benchmark, copy this many MiB with a plain device copy (for counter scaling)")
@@ -123,32 +127,45 @@ def measured_valu(workload_name, kernel):
     return None
 
 
-def cpu_baseline(w, cycles):
-    """The oracle as it stands, single-threaded, on a bounded sample of the
-    workload: `cycles` spkMC cycles of the full lattice (initialisation not timed)."""
-    import oracle
-    t0 = time.perf_counter()
-    sim = oracle.Sim(L=w["L"], d=w["domain"], J=w["J"], H=w["H"], T=w["T"], seed=w["seed"],
-                     rates=0 if w["rates"] == "glauber" else 1,
-                     init={"random": 0, "up": 1, "down": 2}[w["init"]])
-    t_init = time.perf_counter() - t0
-    st0 = sim.state()
-    t0 = time.perf_counter()
-    sim.run(cycles)
-    dt = time.perf_counter() - t0
-    st1 = sim.state()
-    fired = st1[1] - st0[1]
-    model = ""
+def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+            return next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
-        pass
-    return {"value": fired / dt, "unit": "spin-flip events/s", "cores": 1, "kind": "oracle",
-            "host": {"cpu": model, "logical_cpus": os.cpu_count()},
-            "sample": f"{cycles} cycles of the same L={w['L']} d={w['domain']} lattice from the same seed "
-                      f"({fired} events in {dt:.2f} s; initialisation {t_init:.1f} s not timed)",
+        return ""
+
+
+def cpu_baseline(w, cycles, threads=1):
+    """The oracle as it stands on a bounded sample of the workload: `cycles`
+    spkMC cycles of the full lattice (initialisation not timed), its per-domain
+    loops on `threads` host threads (1 = the plain serial loops; the trajectory
+    is the same for every thread count)."""
+    import oracle
+    oracle.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        sim = oracle.Sim(L=w["L"], d=w["domain"], J=w["J"], H=w["H"], T=w["T"], seed=w["seed"],
+                         rates=0 if w["rates"] == "glauber" else 1,
+                         init={"random": 0, "up": 1, "down": 2}[w["init"]])
+        t_init = time.perf_counter() - t0
+        st0 = sim.state()
+        t0 = time.perf_counter()
+        sim.run(cycles)
+        dt = time.perf_counter() - t0
+        st1 = sim.state()
+        del sim
+    finally:
+        oracle.set_threads(1)
+    fired = st1[1] - st0[1]
+    return {"value": fired / dt, "unit": "spin-flip events/s", "cores": oracle_threads_used(threads), "kind": "oracle",
+            "host": {"cpu": _cpu_model(), "logical_cpus": os.cpu_count()},
+            "sample": f"{cycles} cycles of the same L={w['L']} d={w['domain']} lattice from the same seed on "
+                      f"{threads} thread(s) ({fired} events in {dt:.2f} s; initialisation {t_init:.1f} s not timed)",
             "attempts_per_s": (st1[1] + st1[2] - st0[1] - st0[2]) / dt}
+
+
+def oracle_threads_used(threads):
+    return max(1, min(int(threads), os.cpu_count() or 1))
 
 
 def serial_bkl_baseline(events=2_500_000):
@@ -205,6 +222,63 @@ def _serve_run(spkmc, specs, doms, arrivals, pool_bytes, macro, max_live, log):
     log(f"serve: {n} requests, p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms, "
         f"makespan {span:.3f} s, pool peak {st['pool_peak'] / 2**20:.1f} MiB")
     return out, [r["state_tuple"] for r in res]
+
+
+def replica_mix_legs(args, plain_kernel_events, log):
+    """The batched and served forms on the replica mix (256 lattices, L in
+    {32..256}, T in [4, 5], H in {0, +-0.05}, 1000 cycles each), each against
+    the plain path (every lattice alone, one launch after another) and against
+    the plain single-lattice kernel at 1024^3 of the same run; every batched and
+    served lattice is checked bit for bit against its plain run."""
+    import torch
+    from paper_1005_4713_amd import spkmc, tune, workloads
+    specs = workloads.replica_mix(args.replicas)
+    for sp in specs:
+        sp["cycles"] = args.cycles
+    plan, table = tune.tune(specs, probe_cycles=20, log=log)
+    doms = plan["domains"]
+    log("bench: replica mix, plain path")
+    solo = tune.build(specs, doms)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sim in solo:
+        sim.run(args.cycles)
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t0
+    plain = [sim.state() for sim in solo]
+    del solo
+    fired = sum(st[1] for st in plain)
+    plain_rate = fired / dt_plain
+    log("bench: replica mix, batched")
+    sims = tune.build(specs, doms)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tune.run_plan(plan, sims, args.cycles)
+    torch.cuda.synchronize()
+    dt_batch = time.perf_counter() - t0
+    batched = [sim.state() for sim in sims]
+    del sims
+    log("bench: replica mix, served (Poisson arrivals)")
+    foot = sum((spkmc.state_bytes(spkmc.make_params(sp["L"], d)) + 255) // 256 * 256 for sp, d in zip(specs, doms))
+    cap = int(200e9)
+    served, st_served = _serve_run(spkmc, specs, doms, workloads.arrivals(len(specs), rate=50.0, seed=6),
+                                   min(cap, foot), args.macro_cycles, 512, log)
+    return {
+        "batched": {"value": fired / dt_batch, "unit": "spin-flip events/s", "seconds": dt_batch,
+                    "launches": len(plan["launches"]), "domains_policy": plan["policy"], "passes": plan["passes"],
+                    "vs_plain_path": dt_plain / dt_batch, "vs_plain_1024_kernel": fired / dt_batch / plain_kernel_events,
+                    "bit_identical_to_plain": batched == plain},
+        "served": {"p50_ms": served["p50_ms"], "p99_ms": served["p99_ms"], "mean_ms": served["mean_ms"],
+                   "max_ms": served["max_ms"], "events_per_s": served["events_per_s"],
+                   "vs_plain_path": served["events_per_s"] / plain_rate,
+                   "vs_plain_1024_kernel": served["events_per_s"] / plain_kernel_events,
+                   "makespan_s": served["makespan_s"], "arrivals": "Poisson 50/s, seed 6",
+                   "admission_cap_bytes": cap, "mix_footprint_bytes": foot, "macro_cycles": args.macro_cycles,
+                   "bit_identical_to_plain": st_served == plain},
+        "plain_path": {"value": plain_rate, "unit": "spin-flip events/s", "seconds": dt_plain,
+                       "kind": "each lattice alone, one launch after another"},
+        "workload": f"replica_mix_{len(specs)}x{args.cycles}_cycles",
+    }
 
 
 def bench_zeff(args):
@@ -515,10 +589,18 @@ def main():
                      "frac_lower_bound_bytes": (info["K"] * lpd * info["h"] ** 3 / 8.0) * args.steps / secs / 1e9
                      / HBM_PEAK_GBS},
     }
+    del sim
+    torch.cuda.synchronize()
+    if args.workload == "headline" and not args.no_mix:
+        log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+        out["replica_mix"] = replica_mix_legs(args, value, log)
     if not args.no_cpu_baseline:
         cyc = args.cpu_cycles or (12 if w["L"] >= 1024 else 80 if w["L"] >= 512 else 4000)
-        print(f"bench: cpu baseline, {cyc} oracle cycles", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, cyc)
+        nthr = min(16, os.cpu_count() or 1)
+        print(f"bench: cpu baseline, {3 * cyc} oracle cycles on {nthr} threads", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, 3 * cyc, threads=nthr)
+        print(f"bench: cpu baseline, {cyc} oracle cycles on one thread", file=sys.stderr, flush=True)
+        out["cpu_baseline"]["single_thread"] = cpu_baseline(w, cyc, threads=1)
         out["cpu_baseline"]["serial_bkl"] = serial_bkl_baseline()
     print(json.dumps(out), flush=True)
 
