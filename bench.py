@@ -605,5 +605,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def _shutdown():
+    """Release every device object of the library and wait for the device
+    before the interpreter exits (nothing is left for exit-time handlers)."""
+    import gc
+    import torch
+    from paper_1005_4713_amd import spkmc
+    gc.collect()
+    spkmc.release_cached()
+    torch.cuda.synchronize()
+
+
 if __name__ == "__main__":
     main()
+    if "torch" in sys.modules and sys.modules["torch"].cuda.is_initialized():
+        _shutdown()

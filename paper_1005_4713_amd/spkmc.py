@@ -282,6 +282,17 @@ class Sim(_Lattice):
 _workspace = {}
 
 
+def release_cached():
+    """Wait for the device, then drop the batch workspaces this module keeps
+    per stream, so that a program can free every device buffer of the library
+    before the interpreter and the HIP runtime shut down (each Sim, Server or
+    BatchGraph is released by dropping it, or by its close())."""
+    if _workspace:
+        import torch
+        torch.cuda.synchronize()
+        _workspace.clear()
+
+
 def run_batch(sims, ncycles, obs_every=0, wg_domains=0):
     """Run ncycles[i] cycles on each lattice of `sims` (same device, stream and
     octant edge) in one persistent launch; returns the launch shape."""

@@ -29,3 +29,16 @@ def _oracle_threads():
     oracle.set_threads(min(16, os.cpu_count() or 1))
     yield
     oracle.set_threads(1)
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _release_device_objects():
+    """After the last test: drop the library's cached batch workspaces and wait
+    for the device, so nothing of the library is freed by exit-time handlers."""
+    yield
+    import sys as _sys
+    mod = _sys.modules.get("paper_1005_4713_amd.spkmc")
+    if mod is not None:
+        import gc
+        gc.collect()
+        mod.release_cached()
