@@ -136,8 +136,9 @@ typedef struct spkmc_params {
                              (the fewest that fit the device at once); the row count
                              (32 for octant edge 16, 64 for 8) times 1, 2 or 4 passes,
                              for edge 16 also times 8 or 16 (the wide mode: two or
-                             four rounds of four passes).  Other values change the
-                             launch shape, never the results                        */
+                             four rounds of four passes); INCREMENTAL: 32 rows times
+                             1 or 2 passes.  Other values change the launch shape,
+                             never the results                                      */
     uint32_t record_cap;  /* observation records kept on the device (ring)             */
     uint32_t variant;     /* SPKMC_VARIANT_* bits; 0 = 8 colours, R_max over the K
                              active octants                                          */
@@ -254,7 +255,8 @@ size_t spkmc_batch_workspace_bytes(size_t n);
  * stream, each context at most once (E_INVAL otherwise; a context with
  * ncycles 0 is not counted), and the launch must fit on the device at once (E_UNSUPPORTED
  * otherwise: split the batch).  wg_domains: domains per workgroup (0 = the
- * fewest passes that fit).  dev_workspace: spkmc_batch_workspace_bytes(n)
+ * fewest passes that fit; 1, 2 or 4 passes of the row count, at most 2 for
+ * octant edge 8).  dev_workspace: spkmc_batch_workspace_bytes(n)
  * bytes of device memory owned by the caller; it must stay untouched until
  * the launch has finished.  info (may be NULL) receives the launch shape. */
 spkmc_status spkmc_run_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,

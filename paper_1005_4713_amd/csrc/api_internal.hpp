@@ -36,11 +36,15 @@ hipError_t launch_slab(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t ob
                        hipStream_t stream);
 struct Replica;
 size_t replica_bytes();
+// lpd: 1 when every lattice has one line per domain (eight colours; a kernel
+// with that fixed at compile time), 0 otherwise
 hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t *ncycles, uint32_t obs_every,
-                      uint32_t n, int P, Replica *out, int &grid, int &block);
+                      uint32_t n, int P, Replica *out, int &grid, int &block, uint32_t &lpd);
 hipError_t upload_replicas(const Replica *host, uint32_t n, Replica *dev, hipStream_t stream);
-hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipStream_t stream);
-hipError_t capture_batch(Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipGraph_t *graph);
+hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, uint32_t lpd,
+                        hipStream_t stream);
+hipError_t capture_batch(Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, uint32_t lpd,
+                         hipGraph_t *graph);
 // The device array of spkmc_run_batch_static on the current device (resolved
 // on the first call per device), its capacity in lattices and its bytes.
 hipError_t static_replicas(Replica **out);
@@ -71,10 +75,11 @@ struct spkmc_ctx {
 namespace spkmc {
 // Workgroups the batch kernel for octant edge h with P passes can keep resident
 // at once on the current device (0 on error).
-uint32_t batch_capacity(int h, int P);
+uint32_t batch_capacity(int h, int P, uint32_t lpd = 1);
 // Rows (domains per pass) and the most passes of the persistent kernels.
 int persist_rows(int h, bool inc);
 int persist_max_passes(int h, bool inc);
+int batch_max_passes(int h);
 uint32_t batch_wgs(const Geom &g, int P);
 
 // The observables of a lattice of N sites with parameters p from a copy of its

@@ -749,7 +749,9 @@ __global__ void __launch_bounds__(512) k_persistent_wide(Replica R) {
 
 // Many independent lattices in one launch: each workgroup finds its lattice by
 // its workgroup index; lattices never wait for one another.
-template <int H, int P, int BLOCK, bool INC>
+// LPD: 1 when every lattice of the batch has eight colours (one line per domain,
+// fixed at compile time), 0 for batches that mix in two-colour lattices.
+template <int H, int P, int BLOCK, bool INC, int LPD>
 __global__ void __launch_bounds__(BLOCK) k_persistent_batch(const Replica *__restrict__ reps, uint32_t nrep) {
     __shared__ PersistShared sh;
     uint32_t lo = 0, hi = nrep;  // last replica with first_wg <= blockIdx.x
@@ -761,7 +763,7 @@ __global__ void __launch_bounds__(BLOCK) k_persistent_batch(const Replica *__res
     // the index is the same in every lane: keep the descriptor in scalar registers
     const Replica &R = reps[__builtin_amdgcn_readfirstlane(lo)];
     if (blockIdx.x >= R.first_wg + R.G) return;  // a spare workgroup past the last lattice
-    persistent_body<H, P, BLOCK, INC, 0>(R, blockIdx.x - R.first_wg, sh);  // lattices of either line count
+    persistent_body<H, P, BLOCK, INC, LPD>(R, blockIdx.x - R.first_wg, sh);
 }
 
 // Before a launch: slots carry the generation of no cycle of this launch yet,
@@ -798,16 +800,30 @@ __global__ void k_persistent_prep_batch(const Replica *__restrict__ reps, uint32
 // and P passes (1, 2 or 4).  h = 16 keeps up to four passes of class planes in
 // 256 registers with 32 rows (512 threads, two waves per SIMD); h = 8 needs 4
 // registers per pass and runs 64 rows (1024 threads, four waves per SIMD).
-int persist_rows(int h, bool) { return h == 8 ? 64 : 32; }
-int persist_max_passes(int, bool) { return 4; }
+// The incremental engine keeps more state per line than re-binning (counts of
+// all eight octants, pushed changes): 32 rows and at most two passes, so that
+// its kernels fit their registers.
+int persist_rows(int h, bool inc) { return h == 8 && !inc ? 64 : 32; }
+int persist_max_passes(int, bool inc) { return inc ? 2 : 4; }
+// Batches of octant edge 8 (1024 threads, 128 registers) stop at two passes:
+// with four the batch kernel's run-time descriptor spills registers.
+int batch_max_passes(int h) { return h == 8 ? 2 : 4; }
 
+// batch: lpd = 1 (every lattice with eight colours) or 0 (lines per domain read
+// at run time)
 template <int H, int P, int BLOCK>
 static void *kernel_of(bool batch, bool inc, uint32_t lpd) {
-    if (inc) return reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, true, 1>);
-    if (batch) return reinterpret_cast<void *>(&k_persistent_batch<H, P, BLOCK, false>);
+    if (inc) {
+        if constexpr (P <= 2 && BLOCK == 512) return reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, true, 1>);
+        return nullptr;
+    }
+    if (batch)
+        return lpd == 1 ? reinterpret_cast<void *>(&k_persistent_batch<H, P, BLOCK, false, 1>)
+                        : reinterpret_cast<void *>(&k_persistent_batch<H, P, BLOCK, false, 0>);
     return lpd == 4 ? reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false, 4>)
                     : reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false, 1>);
 }
+
 // The wide mode's rounds for one lattice: 1 (passes only), 2 or 4 (octant edge 16,
 // re-binning engine).
 static int max_rounds(int h, bool inc) { return h == 16 && !inc ? 4 : 1; }
@@ -831,11 +847,13 @@ static void *select_kernel(int h, int P, int block, bool batch = false, bool inc
                : P == 2 ? kernel_of<16, 2, 512>(batch, inc, lpd)
                : P == 4 ? kernel_of<16, 4, 512>(batch, inc, lpd)
                         : nullptr;
-    if (h == 8 && block == 1024)
+    if (h == 8 && block == 1024 && !inc)
         return P == 1   ? kernel_of<8, 1, 1024>(batch, inc, lpd)
                : P == 2 ? kernel_of<8, 2, 1024>(batch, inc, lpd)
                : P == 4 ? kernel_of<8, 4, 1024>(batch, inc, lpd)
                         : nullptr;
+    if (h == 8 && block == 512 && inc && !batch)
+        return P == 1 ? kernel_of<8, 1, 512>(false, true, 1) : P == 2 ? kernel_of<8, 2, 512>(false, true, 1) : nullptr;
     return nullptr;
 }
 
@@ -950,9 +968,9 @@ uint32_t batch_wgs(const Geom &g, int P) {
 
 // Workgroups of the batch kernel for octant edge h and P passes that the
 // current device keeps resident at once (0 on error).
-uint32_t batch_capacity(int h, int P) {
+uint32_t batch_capacity(int h, int P, uint32_t lpd) {
     const int block = persist_rows(h, false) * 16;
-    void *kern = select_kernel(h, P, block, true);
+    void *kern = select_kernel(h, P, block, true, false, lpd);
     if (!kern) return 0;
     int dev = 0, cus = 0, occ = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -964,11 +982,14 @@ uint32_t batch_capacity(int h, int P) {
 
 // Fill the descriptors (host memory) and check the launch fits on the device.
 hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t *ncycles, uint32_t obs_every,
-                      uint32_t n, int P, Replica *out, int &grid, int &block) {
+                      uint32_t n, int P, Replica *out, int &grid, int &block, uint32_t &lpd) {
     if (n == 0) return hipErrorInvalidValue;
     const int h = gs[0]->h;
     block = persist_rows(h, false) * 16;
-    void *kern = select_kernel(h, P, block, true);
+    lpd = 1;
+    for (uint32_t i = 0; i < n; ++i)
+        if (gs[i]->lpd != 1) lpd = 0;
+    void *kern = select_kernel(h, P, block, true, false, lpd);
     if (!kern) return hipErrorInvalidValue;
     uint32_t first = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -983,7 +1004,7 @@ hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t 
         out[i].pad = 0;
         first += out[i].G;
     }
-    const uint32_t cap = batch_capacity(h, P);
+    const uint32_t cap = batch_capacity(h, P, lpd);
     if (cap == 0) return hipErrorInvalidValue;
     if (first > cap) return hipErrorCooperativeLaunchTooLarge;
     grid = (int)first;
@@ -1056,8 +1077,9 @@ __global__ void k_advance_batch(Replica *reps, uint32_t nrep) {
 }
 
 // The descriptors must already be in device memory (dev_reps).
-hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipStream_t stream) {
-    void *kern = select_kernel(h, P, block, true);
+hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, uint32_t lpd,
+                        hipStream_t stream) {
+    void *kern = select_kernel(h, P, block, true, false, lpd);
     if (!kern) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_persistent_prep_batch, dim3(n < 256 ? n : 256), dim3(256), 0, stream, dev_reps, n, 0);
     hipError_t e = hipGetLastError();
@@ -1071,8 +1093,9 @@ hipError_t launch_batch(const Replica *dev_reps, uint32_t n, int h, int P, int g
 // the batch kernel (a cooperative node: every workgroup resident at once, as
 // for hipLaunchCooperativeKernel, which stream capture does not take), and the
 // descriptor advance.  The descriptors must already be in device memory.
-hipError_t capture_batch(Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, hipGraph_t *graph) {
-    void *kern = select_kernel(h, P, block, true);
+hipError_t capture_batch(Replica *dev_reps, uint32_t n, int h, int P, int grid, int block, uint32_t lpd,
+                         hipGraph_t *graph) {
+    void *kern = select_kernel(h, P, block, true, false, lpd);
     if (!kern || n == 0) return hipErrorInvalidValue;
     hipGraph_t g = nullptr;
     hipError_t e = hipGraphCreate(&g, 0);

@@ -543,6 +543,7 @@ struct BatchPlan {
     std::vector<unsigned char> host;  // the descriptors (replica_bytes() each)
     hipStream_t stream = nullptr;
     int h = 0, grid = 0, block = 0, P = 0;
+    uint32_t lpd = 1;  // every lattice with one line per domain (else 0)
 };
 
 static spkmc_status plan_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t *ncycles, uint32_t obs_every,
@@ -573,7 +574,7 @@ static spkmc_status plan_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t 
         bp.nc.push_back(ncycles[i]);
     }
     if (bp.live.empty()) return SPKMC_OK;
-    const int rows = persist_rows(bp.h, false), pmax = persist_max_passes(bp.h, false);
+    const int rows = persist_rows(bp.h, false), pmax = batch_max_passes(bp.h);
     std::vector<int> Ps;
     if (wg_domains) {
         const int pc = wg_domains / rows;
@@ -589,7 +590,7 @@ static spkmc_status plan_batch(spkmc_ctx *const *ctxs, size_t n, const uint64_t 
     hipError_t e = hipErrorCooperativeLaunchTooLarge;
     for (int Pc : Ps) {
         e = batch_plan(gs.data(), n0.data(), bp.nc.data(), obs_every, (uint32_t)bp.live.size(), Pc, reps, bp.grid,
-                       bp.block);
+                       bp.block, bp.lpd);
         if (e == hipSuccess) {
             bp.P = Pc;
             break;
@@ -630,7 +631,7 @@ extern "C" {
 static spkmc_status launch_planned(BatchPlan &bp, Replica *dev_reps, spkmc_batch_info *info) {
     const uint32_t nl = (uint32_t)bp.live.size();
     hipError_t e = upload_replicas(reinterpret_cast<const Replica *>(bp.host.data()), nl, dev_reps, bp.stream);
-    if (e == hipSuccess) e = launch_batch(dev_reps, nl, bp.h, bp.P, bp.grid, bp.block, bp.stream);
+    if (e == hipSuccess) e = launch_batch(dev_reps, nl, bp.h, bp.P, bp.grid, bp.block, bp.lpd, bp.stream);
     if (e != hipSuccess) {
         for (spkmc_ctx *c : bp.live) c->failed = true;
         return fail(nullptr, SPKMC_E_DEVICE, std::string("batch launch: ") + hipGetErrorString(e));
@@ -689,7 +690,7 @@ spkmc_status spkmc_batch_graph_create(spkmc_ctx *const *ctxs, size_t n, const ui
         gr->expect.push_back(c->cycle);
         c->primed_grid = 0;
     }
-    e = capture_batch(dev_reps, nl, bp.h, bp.P, bp.grid, bp.block, &gr->graph);
+    e = capture_batch(dev_reps, nl, bp.h, bp.P, bp.grid, bp.block, bp.lpd, &gr->graph);
     if (e == hipSuccess) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         spkmc_batch_graph_destroy(gr);

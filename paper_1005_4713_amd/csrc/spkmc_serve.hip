@@ -199,7 +199,7 @@ static spkmc_status admit(spkmc_server *s) {
         std::string why;
         const int h = r.ctx->g.h;
         r.batched = persistent_supported(r.ctx->g, r.ctx->p, false, why) &&
-                    batch_wgs(r.ctx->g, persist_max_passes(h, false)) <= s->cap[h == 16];
+                    batch_wgs(r.ctx->g, batch_max_passes(h)) <= s->cap[h == 16];
         r.state = SPKMC_REQ_RUNNING;
         s->live.push_back(r.id);
     }
@@ -208,7 +208,7 @@ static spkmc_status admit(spkmc_server *s) {
 
 // First fit by decreasing workgroups into launches the device holds at once.
 static std::vector<std::vector<Request *>> pack(std::vector<Request *> rs, uint32_t cap) {
-    auto wgs = [](const Request *r) { return batch_wgs(r->ctx->g, persist_max_passes(r->ctx->g.h, false)); };
+    auto wgs = [](const Request *r) { return batch_wgs(r->ctx->g, batch_max_passes(r->ctx->g.h)); };
     std::sort(rs.begin(), rs.end(), [&](Request *a, Request *b) {
         uint32_t wa = wgs(a), wb = wgs(b);
         return wa != wb ? wa > wb : a->id < b->id;
@@ -382,8 +382,8 @@ spkmc_status spkmc_server_create(const spkmc_server_config *cfg, void *dev_pool,
     }
     memset((void *)s->pinned, 0, slots * sizeof(DevState));
     for (size_t i = slots; i-- > 0;) s->free_slots.push_back((int)i);
-    s->cap[0] = batch_capacity(8, persist_max_passes(8, false));
-    s->cap[1] = batch_capacity(16, persist_max_passes(16, false));
+    s->cap[0] = batch_capacity(8, batch_max_passes(8));
+    s->cap[1] = batch_capacity(16, batch_max_passes(16));
     s->t0 = std::chrono::steady_clock::now();
     *out = s;
     return SPKMC_OK;

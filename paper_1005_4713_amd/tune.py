@@ -22,7 +22,7 @@ import torch
 from . import spkmc
 
 ROWS = {8: 64, 16: 32}
-MAX_PASSES = {8: 4, 16: 4}
+MAX_PASSES = {8: 2, 16: 4}  # batches of octant edge 8 stop at two passes (registers)
 
 
 def domain_choices(L):

@@ -69,10 +69,13 @@ def test_batch_member_vs_oracle(spkmc):
     assert np.array_equal(batch[0].spins(), orc.spins())
 
 
-def test_batch_launch_shapes_identical(spkmc):
-    mix = _mix(16, [64, 128, 96], 11)
+@pytest.mark.parametrize("d,shapes", [(16, (64, 128)), (32, (32, 64, 128))])
+def test_batch_launch_shapes_identical(spkmc, d, shapes):
+    """One to two passes of 64 rows for octant edge 8, one to four of 32 rows
+    for edge 16: the same lattices bit for bit."""
+    mix = _mix(d, [64, 128, 96], 11)
     ref = None
-    for wd in (64, 128, 256):
+    for wd in shapes:
         sims = _sims(spkmc, mix)
         info = spkmc.run_batch(sims, 90, obs_every=9, wg_domains=wd)
         assert info["wg_domains"] == wd
@@ -81,6 +84,12 @@ def test_batch_launch_shapes_identical(spkmc):
             ref = out
         else:
             assert out == ref
+
+
+def test_batch_edge8_four_passes_refused(spkmc):
+    sims = _sims(spkmc, _mix(16, [64], 12))
+    with pytest.raises(spkmc.SpkmcError):
+        spkmc.run_batch(sims, 10, wg_domains=256)
 
 
 def test_batch_rejects_mixed_edges(spkmc):
