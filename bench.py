@@ -282,7 +282,7 @@ def replica_mix_legs(args, plain_kernel_events, log):
 
 
 def bench_zeff(args):
-    """Sec. 5 analysis (eqs. 16-17): magnetisation relaxation from all +1 at
+    """Sec. 6 analysis (eqs. 16-17): magnetisation relaxation from all +1 at
     T_c, m(t) ~ t^(-beta / (nu z)); the effective exponent from the log-slope
     over sliding windows, z_eff = -(beta/nu) / (d ln m / d ln t), with the
     paper's beta/nu = 0.515.  Time in units of 1/lambda (lambda = 1)."""
