@@ -68,6 +68,8 @@ struct PersistSharedT {
     uint32_t selq[DMAX];        // per line: (class << 12) | site q of its event, or kNoEvent
     double rpred[8];                   // per colour: the last R_max seen (the prediction)
     double rmax;
+    double next_lnu;                   // -ln u of the next cycle's clock step
+    int next_colour;                   // the next cycle's colour
     int abort;
     uint32_t nbr_bits[6][kMaxGrid / 32];  // neighbour workgroups per direction, as a bitmap
     uint32_t nbr_cnt[6];                  // > kMaxNbr: too many, wait for every workgroup
@@ -203,15 +205,21 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     uint32_t rec_index = 0;                  // records produced in this launch
     int prev_colour = -1;
     const bool bound = (g.variant & SPKMC_VARIANT_RMAX_BOUND) != 0;   // re-binning engine only
+    // the bound as a value: a conditional read of it or of an LDS word would be a
+    // generic (flat) load, whose wait also waits for this wavefront's slot store
+    const double rbound = g.rbound;
     const bool rmax_all = INC && (g.variant & SPKMC_VARIANT_RMAX_ALL);  // incremental engine only
-    // -ln u of the coming cycle's clock step
-    double lnu = -log(cycle_draw(g.seed, n0, lpd == 4).ut);
+    // the coming cycle's colour, and -ln u of its clock step (wavefront 0 keeps
+    // the clock; the other wavefronts' t is never used)
+    const CycleDraw cd0 = cycle_draw(g.seed, n0, lpd == 4);
+    int s_next = cd0.colour;
+    double lnu = 0.0;
+    if (tid < 64) lnu = -log(cd0.ut);
     // the cycle after which the next observation record falls due
     uint64_t next_rec = obs_every ? (n0 / obs_every + 1) * obs_every : ~0ull;
 
     for (uint64_t n = n0; n < n_end; ++n) {
-        CycleDraw cd = cycle_draw(g.seed, n, lpd == 4);
-        const int s = cd.colour;  // the octant (eight colours) or the parity (two)
+        const int s = s_next;  // the octant (eight colours) or the parity (two)
 
         // --- step 6 of the previous cycle: wait for the neighbour flips the halo of colour s can see.
         // With the fixed bound (no R_max exchange) or the all-octant maximum (every
@@ -425,7 +433,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         };
         uint32_t cpred = 0;  // per pass: predicted class + 1, five bits each
         if constexpr (RND == 1) {
-            const double Rspec = bound ? g.rbound : sh.rpred[s];
+            const double Rspec = bound ? rbound : sh.rpred[s];
 #pragma unroll
             for (int pp = 0; pp < P; ++pp) {
                 const uint32_t ld = (uint32_t)(pp * rows + row);
@@ -434,6 +442,13 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                 cpred |= (uint32_t)(cs + 1) << (5 * pp);
                 select_site<H>(pl[pp], cs, cs >= 0 ? line_count(ld, cs) : 0u, uz, l, &sh.selq[ld], st);
             }
+        }
+
+        // the next cycle's draw, by wavefront 1 while wavefront 0 polls
+        if (tid == 64) {
+            const CycleDraw nd = cycle_draw(g.seed, n + 1, lpd == 4);
+            sh.next_colour = nd.colour;
+            sh.next_lnu = -log(nd.ut);
         }
 
         if (tid < 64 && !bound) {
@@ -478,7 +493,8 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         }
         __syncthreads();
         if (sh.abort) break;
-        const double Rmax = bound ? g.rbound : sh.rmax;
+        const double Rmax = bound ? rbound : sh.rmax;
+        s_next = sh.next_colour;
 
         if constexpr (RND > 1) {
             // --- steps 3, 4 and 4b, wide mode: every round's class planes from its
@@ -592,11 +608,11 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         __builtin_amdgcn_s_waitcnt(0);
 
         // --- step 5: the clock, identical in every workgroup
-        {
+        if (tid < 64) {
             double dt = lnu / ((lpd == 4 ? 2.0 : 8.0) * Rmax);
             t = t + dt;
+            lnu = sh.next_lnu;
         }
-        lnu = -log(cycle_draw(g.seed, n + 1, lpd == 4).ut);
         // flips complete, then publish them (step 6)
         __syncthreads();
 
