@@ -63,7 +63,7 @@ struct PersistSharedT {
     uint32_t histp[HISTP ? DMAX : 1][8][7];  // per domain and octant: packed class counts (incremental engine)
     double acc[DMAX][14];       // per line: running FP64 sums of the frequency line
     double rk[DMAX];
-    uint32_t zbuf[64][24];      // per row: z face words below (8), above (8), zeros (8)
+    alignas(16) uint32_t zbuf[64][kRowHalo];  // per row: the six halo faces (8 words each), zeros (8)
     uint32_t nbdom[DMAX][6];    // per line: its domain's neighbour domains -x, +x, -y, +y, -z, +z
     uint32_t selq[DMAX];        // per line: (class << 12) | site q of its event, or kNoEvent
     double rpred[8];                   // per colour: the last R_max seen (the prediction)
@@ -169,7 +169,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     }
     load_predictions(sh, xs);
     if (tid < 14) sh.r[tid] = g.r[tid];
-    if (l < 8) sh.zbuf[row][16 + l] = 0;
+    if (l < 8) sh.zbuf[row][48 + l] = 0;
     for (uint32_t i = tid; i < nvalid * 6; i += nthr) {
         uint32_t ldm = i / 6;
         int dir = (int)(i % 6), a = dir >> 1;

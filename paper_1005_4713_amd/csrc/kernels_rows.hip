@@ -20,7 +20,7 @@ namespace spkmc {
 constexpr int kRowsPasses = 4;  // passes of the row kernels (128 or 256 lines per workgroup)
 
 struct RowsShared {
-    uint32_t zbuf[64][24];             // per row: z face words below (8), above (8), zeros (8)
+    alignas(16) uint32_t zbuf[64][kRowHalo];  // per row: the six halo faces (8 words each), zeros (8)
     uint32_t nbdom[kMaxWgDomains][6];  // per line: its domain's six neighbour domains
     double acc[kMaxWgDomains][14];     // per line: running FP64 sums of the frequency line
     uint32_t hist[kMaxWgDomains][14];  // per line: class counts
@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(BLOCK) k_rows_bin(Geom g, uint64_t n) {
     const int s = cycle_draw(g.seed, n, rg.lpd == 4).colour;
     rg.neighbours(sh.nbdom);
     if (tid == 0) sh.wmax = 0;
-    if (l < 8) sh.zbuf[row][16 + l] = 0;
+    if (l < 8) sh.zbuf[row][48 + l] = 0;
     __syncthreads();
     Raw<H> raw[P];
 #pragma unroll
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(BLOCK) k_rows_select(Geom g, uint64_t n) {
     const int s = cycle_draw(g.seed, n, rg.lpd == 4).colour;
     const double Rmax = (g.variant & SPKMC_VARIANT_RMAX_BOUND) ? g.rbound : bits_to_double(g.st->rmax[0]);
     rg.neighbours(sh.nbdom);
-    if (l < 8) sh.zbuf[row][16 + l] = 0;
+    if (l < 8) sh.zbuf[row][48 + l] = 0;
     // the counts of every line and their running sums, in the order of step 1
     for (uint32_t i = tid; i < D; i += BLOCK) {
         double a = 0.0;

@@ -34,12 +34,12 @@ constexpr int kFxm = 128, kFxp = 136, kFym = 144, kFyp = 152, kFzm = 160, kFzp =
 
 struct SlabShared {
     double r[14];
-    uint32_t oct[kSlabDomains][kOctLds];    // active octants and their halos
+    alignas(16) uint32_t oct[kSlabDomains][kOctLds];    // active octants and their halos
     uint32_t sc[kSlabDomains][kSlabWords];  // slab counts of the active octants
     uint16_t cnt[kSlabDomains][8][14];      // class counts (the active octant; every octant for the all-octant R_max)
     double acc[kSlabDomains][14];           // running FP64 sums of the frequency lines
     double rk[kSlabDomains];
-    uint32_t zbuf[kSlabRows][24];           // binning at launch start: z face words per row
+    alignas(16) uint32_t zbuf[kSlabRows][kRowHalo];     // binning at launch start: halo faces per row
     uint32_t nbdom[kSlabDomains][6];
     uint32_t dco[kSlabDomains];             // domain coordinates kx | ky << 10 | kz << 20
     uint32_t selq[kSlabDomains];
@@ -310,7 +310,7 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
     }
     load_predictions(sh, xs);
     if (tid < 14) sh.r[tid] = g.r[tid];
-    if (l < 8) sh.zbuf[row][16 + l] = 0;
+    if (l < 8) sh.zbuf[row][48 + l] = 0;
     for (uint32_t i = tid; i < nvalid * 6; i += nthr) {
         uint32_t ldm = i / 6;
         int dir = (int)(i % 6), a = dir >> 1;
@@ -495,13 +495,8 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
                     uint32_t *o = sh.oct[ld];
 #pragma unroll
                     for (int w = 0; w < 8; ++w) o[8 * l + w] = raw[pp].W[w];
-                    if (!(l & 1)) {
-                        o[kFxm + (l >> 1)] = raw[pp].xm;
-                        o[kFxp + (l >> 1)] = raw[pp].xp;
-                        o[kFym + (l >> 1)] = raw[pp].ym;
-                        o[kFyp + (l >> 1)] = raw[pp].yp;
-                    }
-                    o[kFzm + l] = raw[pp].zw;  // lanes 8 .. 15: the face above
+                    // the six faces in the order of kFxm .. kFzp (one quarter-face per lane)
+                    if (l < 12) *reinterpret_cast<uint4 *>(o + kFxm + 4 * l) = uint4{raw[pp].F[0], raw[pp].F[1], raw[pp].F[2], raw[pp].F[3]};
                 }
                 const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
                 const int cs = row_class(sh.acc[ld], ld < nvalid, unit53(ux, uy) * Rspec, l, row);
@@ -718,13 +713,13 @@ __global__ void __launch_bounds__(kSlabBlock) k_slab(Replica R) {
 // run by k_slab_bin; kernel boundaries order every read after the writes it needs.
 // ---------------------------------------------------------------------------
 struct SrowsShared {
-    uint32_t oct[kSlabDomains][kOctLds];
+    alignas(16) uint32_t oct[kSlabDomains][kOctLds];
     uint32_t sc[kSlabDomains][kSlabWords];
     double acc[kSlabDomains][14];
     uint32_t nbdom[kSlabDomains][6];
     uint32_t dco[kSlabDomains];
     uint32_t selq[kSlabDomains];
-    uint32_t zbuf[kSlabRows][24];
+    alignas(16) uint32_t zbuf[kSlabRows][kRowHalo];
     unsigned long long wmax;
     long long red[3][16];
 };
@@ -743,7 +738,7 @@ __global__ void __launch_bounds__(kSlabBlock) k_slab_bin(Geom g) {
         kc[a] = (dir & 1) ? wrapp(kc[a], g.nd) : wrapm(kc[a], g.nd);
         sh.nbdom[ldm][dir] = dindex(kc[0], kc[1], kc[2], g.nd);
     }
-    if (l < 8) sh.zbuf[row][16 + l] = 0;
+    if (l < 8) sh.zbuf[row][48 + l] = 0;
     __syncthreads();
 #pragma unroll 1
     for (int o = 0; o < 8; ++o) slab_bin_octant(g, kbase, nvalid, o, sh);
@@ -820,13 +815,7 @@ __global__ void __launch_bounds__(kSlabBlock) k_srows_select(Geom g, uint64_t n)
         uint32_t *oc = sh.oct[ld];
 #pragma unroll
         for (int w = 0; w < 8; ++w) oc[8 * l + w] = raw.W[w];
-        if (!(l & 1)) {
-            oc[kFxm + (l >> 1)] = raw.xm;
-            oc[kFxp + (l >> 1)] = raw.xp;
-            oc[kFym + (l >> 1)] = raw.ym;
-            oc[kFyp + (l >> 1)] = raw.yp;
-        }
-        oc[kFzm + l] = raw.zw;
+        if (l < 12) *reinterpret_cast<uint4 *>(oc + kFxm + 4 * l) = uint4{raw.F[0], raw.F[1], raw.F[2], raw.F[3]};
     }
     __syncthreads();
     // running sums of every line, in the order of step 1

@@ -243,9 +243,11 @@ template <int H>
 struct Raw;
 template <>
 struct Raw<16> {
-    uint32_t W[8];            // own plane: word p = rows 2p, 2p + 1
-    uint32_t xm, xp, ym, yp;  // words holding this plane's halo rows in the x and y faces
-    uint32_t zw;              // lanes 0..7: word l of the face below, lanes 8..15: word l-8 of the face above
+    uint32_t W[8];  // own plane: word p = rows 2p, 2p + 1
+    // the octant's six halo faces (8 words each: x below, x above, y below, y
+    // above, z below, z above), a quarter-face per lane: lane j < 12 holds words
+    // 4 (j & 1) .. 4 (j & 1) + 3 of face j / 2; lanes 12 .. 15 hold zeros
+    uint32_t F[4];
 };
 template <>
 struct Raw<8> {
@@ -268,34 +270,46 @@ __device__ __forceinline__ void load16_words(const Geom &g, uint32_t k, int s, b
         r.W[p + 3] = v[3];
     }
 }
-// the halo words of the axes in the mask `axes` (bit a: axis a)
+// The six halo faces: one 16-byte device-coherent load per lane (a face copy is
+// 8 words at a 32-byte aligned address).
 __device__ __forceinline__ void load16_faces(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
-                                             int axes, Raw<16> &r) {
+                                             Raw<16> &r) {
     const HaloFaces hf = halo_faces<16>(k, s, nb);
     const Views vw = views_of(g);
-    // x faces: bit ly + 16 lz -> half-word l; y faces: bit lx + 16 lz -> half-word l
-    if (axes & 1) {
-        r.xm = ld_face(vw, valid, hf.lo[0] + (l >> 1));
-        r.xp = ld_face(vw, valid, hf.hi[0] + (l >> 1));
-    }
-    if (axes & 2) {
-        r.ym = ld_face(vw, valid, hf.lo[1] + (l >> 1));
-        r.yp = ld_face(vw, valid, hf.hi[1] + (l >> 1));
-    }
-    // z faces (bit lx + 16 ly, the layout of a plane), one word per lane
-    if (axes & 4) r.zw = ld_face(vw, valid, (l < 8 ? hf.lo[2] : hf.hi[2]) + (l & 7));
+    // face f = l / 2 (selects, not an indexed read: the faces stay in registers)
+    const int f = l >> 1;
+    uint32_t base = hf.lo[0];
+    base = f == 1 ? hf.hi[0] : base;
+    base = f == 2 ? hf.lo[1] : base;
+    base = f == 3 ? hf.hi[1] : base;
+    base = f == 4 ? hf.lo[2] : base;
+    base = f == 5 ? hf.hi[2] : base;
+    const int off = valid && l < 12 ? (int)((base + 4u * (uint32_t)(l & 1)) * 4u) : vw.endF;
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(vw.F, off, 0, kCoherent);
+    r.F[0] = v[0];
+    r.F[1] = v[1];
+    r.F[2] = v[2];
+    r.F[3] = v[3];
 }
 
-// zrow: this row's 24 LDS words: face below (8), face above (8), zeros (8).
+// zrow: this row's kRowHalo LDS words: the six halo faces (8 words each, in the
+// order of Raw<16>::F), then 8 zeros.
+constexpr int kRowHalo = 56;
 // MOM: also accumulate the 13 popcount moments of the octant.
 template <bool MOM>
 __device__ __forceinline__ void compute16(const Raw<16> &r, bool valid, int l, uint32_t *zrow, Planes<16> &P,
                                           uint32_t (&m)[13]) {
-    zrow[l] = r.zw;  // the row's own lanes read these back (same wavefront)
-    const uint32_t *zlo = zrow + (l == 0 ? 0 : 16), *zhi = zrow + (l == 15 ? 8 : 16);
+    // the faces into the row's LDS words; the row's own lanes read them back (same wavefront)
+    if (l < 12) *reinterpret_cast<uint4 *>(zrow + 4 * l) = uint4{r.F[0], r.F[1], r.F[2], r.F[3]};
+    // the reads below take words other lanes wrote: no reordering across this point
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t *zlo = zrow + (l == 0 ? 32 : 48), *zhi = zrow + (l == 15 ? 40 : 48);
+    // x faces: bit ly + 16 lz -> half-word l of the face; y faces: bit lx + 16 lz -> half-word l
     const uint32_t sh16 = 16 * (l & 1);
-    const uint32_t xm = (r.xm >> sh16) & 0xFFFFu, xp = (r.xp >> sh16) & 0xFFFFu;
-    const uint32_t ym = (r.ym >> sh16) & 0xFFFFu, yp = (r.yp >> sh16) & 0xFFFFu;
+    const uint32_t xm = (zrow[l >> 1] >> sh16) & 0xFFFFu, xp = (zrow[8 + (l >> 1)] >> sh16) & 0xFFFFu;
+    const uint32_t ym = (zrow[16 + (l >> 1)] >> sh16) & 0xFFFFu, yp = (zrow[24 + (l >> 1)] >> sh16) & 0xFFFFu;
     // x halo bits: word p needs xm bits 2p, 2p+1 at bits 0, 16 and xp bits 2p, 2p+1 at 15, 31
     const uint32_t Tm = xm | (xm << 15), Tp = xp | (xp << 15);
 #pragma unroll
@@ -376,15 +390,15 @@ __device__ __forceinline__ void load_words(const Geom &g, uint32_t k, int s, boo
 }
 template <int H>
 __device__ __forceinline__ void load_faces(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
-                                           int axes, Raw<H> &r) {
-    if constexpr (H == 16) load16_faces(g, k, s, valid, l, nb, axes, r);
-    else load8_faces(g, k, s, valid, l, nb, axes, r);
+                                           Raw<H> &r) {
+    if constexpr (H == 16) load16_faces(g, k, s, valid, l, nb, r);
+    else load8_faces(g, k, s, valid, l, nb, 7, r);
 }
 template <int H>
 __device__ __forceinline__ void load_octant(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
                                             Raw<H> &r) {
     load_words<H>(g, k, s, valid, l, r);
-    load_faces<H>(g, k, s, valid, l, nb, 7, r);
+    load_faces<H>(g, k, s, valid, l, nb, r);
 }
 template <int H, bool MOM>
 __device__ __forceinline__ void compute_octant(const Raw<H> &r, bool valid, int l, uint32_t *zrow, Planes<H> &P,
