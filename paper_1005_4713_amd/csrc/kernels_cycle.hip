@@ -63,27 +63,42 @@ __global__ void k_init_packed(Geom g, int init) {
     g.A[wi] = word;
 }
 
-// Face copies of every octant, rebuilt from the packed spins.
-// Face f of an octant: x0 (lx = 0), x1 (lx = h-1), y0, y1, z0, z1; inside a face
-// the bit index is (ly + h lz) for x faces, (lx + h lz) for y, (lx + h ly) for z.
+// The octant across face `a` (axis) of octant (k, s): below (side 0) or above
+// (side 1), in this domain or the neighbour domain (periodic).
+__device__ inline uint64_t octant_across(const Geom &g, uint32_t k, int s, int a, int side) {
+    const uint32_t nd = (uint32_t)g.nd;
+    uint32_t kc[3] = {k % nd, (k / nd) % nd, k / (nd * nd)};
+    const int sa = (s >> a) & 1;
+    if (sa == side) kc[a] = side ? (kc[a] + 1 == nd ? 0 : kc[a] + 1) : (kc[a] == 0 ? nd - 1 : kc[a] - 1);
+    return ((uint64_t)(kc[0] + nd * (kc[1] + nd * kc[2]))) * 8 + (uint64_t)(s ^ (1 << a));
+}
+
+// Halo copies of every octant, rebuilt from the packed spins.  Halo slot f of
+// an octant: x below, x above, y below, y above, z below, z above: the layer at
+// local coordinate h - 1 of the octant below along the axis (slots 0, 2, 4) or
+// layer 0 of the octant above (1, 3, 5).  Inside a slot the bit index is
+// (ly + h lz) for x, (lx + h lz) for y, (lx + h ly) for z.
 __global__ void k_build_faces(Geom g) {
     uint64_t fw = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t total = (uint64_t)g.K * 8 * g.fwpo;
     if (fw >= total) return;
     uint64_t oct = fw / g.fwpo;
+    const uint32_t k = (uint32_t)(oct >> 3);
+    const int s = (int)(oct & 7u);
     uint32_t base_bit = (uint32_t)(fw % g.fwpo) * 32;
-    const uint32_t *octA = g.A + oct * g.wpo;
     uint32_t word = 0;
     for (int b = 0; b < 32; ++b) {
         uint32_t fb = base_bit + b;
         uint32_t f = fb / g.h2, idx = fb % g.h2;
-        uint32_t u = idx % g.h, v = idx / g.h, e = (f & 1) ? g.h - 1 : 0;
+        const int a = (int)(f >> 1), side = (int)(f & 1);
+        const uint32_t *srcA = g.A + octant_across(g, k, s, a, side) * g.wpo;
+        uint32_t u = idx % g.h, v = idx / g.h, e = side ? 0 : g.h - 1;
         uint32_t lx, ly, lz;
-        if (f < 2) { lx = e; ly = u; lz = v; }
-        else if (f < 4) { lx = u; ly = e; lz = v; }
+        if (a == 0) { lx = e; ly = u; lz = v; }
+        else if (a == 1) { lx = u; ly = e; lz = v; }
         else { lx = u; ly = v; lz = e; }
         uint32_t q = lx + g.h * (ly + g.h * lz);
-        word |= ((octA[q >> 5] >> (q & 31)) & 1u) << b;
+        word |= ((srcA[q >> 5] >> (q & 31)) & 1u) << b;
     }
     g.F[fw] = word;
 }
@@ -235,16 +250,19 @@ __global__ void __launch_bounds__(256) k_select(Geom g, uint64_t n) {
                         } else {
                             uint64_t bit = ((uint64_t)k * 8 + (uint64_t)so) * g.h3 + q;
                             atomicXor(&g.A[bit >> 5], 1u << (bit & 31));
-                            uint32_t lx = q % g.h, ly = (q / g.h) % g.h, lz = q / g.h2;
-                            uint32_t *F = g.F + ((uint64_t)k * 8 + (uint64_t)so) * g.fwpo;
-                            uint32_t e = g.h - 1;
-                            uint32_t fidx[6] = {lx == 0 ? ly + g.h * lz : ~0u, lx == e ? g.h2 + ly + g.h * lz : ~0u,
-                                                ly == 0 ? 2 * g.h2 + lx + g.h * lz : ~0u,
-                                                ly == e ? 3 * g.h2 + lx + g.h * lz : ~0u,
-                                                lz == 0 ? 4 * g.h2 + lx + g.h * ly : ~0u,
-                                                lz == e ? 5 * g.h2 + lx + g.h * ly : ~0u};
-                            for (int fc = 0; fc < 6; ++fc)
-                                if (fidx[fc] != ~0u) atomicXor(&F[fidx[fc] >> 5], 1u << (fidx[fc] & 31));
+                            // the halo copies of the octants across the boundary layers it lies on
+                            const uint32_t c3[3] = {q % g.h, (q / g.h) % g.h, q / g.h2};
+                            for (int a = 0; a < 3; ++a) {
+                                if (c3[a] != 0 && c3[a] != g.h - 1) continue;
+                                for (int side = 0; side < 2; ++side) {
+                                    // layer 0 is in the halo above of the octant below (side 0)
+                                    if (c3[a] != (side ? g.h - 1 : 0)) continue;
+                                    const uint32_t u = a == 0 ? c3[1] : c3[0], v = a == 2 ? c3[1] : c3[2];
+                                    const uint32_t b = (uint32_t)(2 * a + (side ? 0 : 1)) * g.h2 + u + g.h * v;
+                                    uint32_t *Ft = g.F + octant_across(g, k, so, a, side) * g.fwpo;
+                                    atomicXor(&Ft[b >> 5], 1u << (b & 31));
+                                }
+                            }
                         }
                         fired += 1;
                         dM += -2 * s;

@@ -598,7 +598,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                 if (ax != 0) continue;
                 hmove(sh.histp[ld][so], cs, site_class(!up, up ? cs - 7 : 6 - cs));
             }
-            flip_site<H>(g, k, so, q);
+            flip_site<H>(g, k, so, q, sh.nbdom[ld]);
             myF += 1;
             mydM += cs >= 7 ? -2 : 2;              // the class carries the old spin
             mydB += 12 - 4 * (long long)(cs % 7);  // and its aligned count

@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(BLOCK) k_rows_select(Geom g, uint64_t n) {
         const uint32_t f = sh.selq[t];
         if (t >= rg.nvalid || f == kNoEvent) continue;
         const uint32_t cs = f >> 12, q = f & 0xFFFu;
-        flip_site<H>(g, rg.dom(rg.kbase + t), rg.oct(rg.kbase + t, s), q);
+        flip_site<H>(g, rg.dom(rg.kbase + t), rg.oct(rg.kbase + t, s), q, sh.nbdom[t]);
         F += 1;
         dM += cs >= 7 ? -2 : 2;              // the class carries the old spin
         dB += 12 - 4 * (long long)(cs % 7);  // and its aligned count

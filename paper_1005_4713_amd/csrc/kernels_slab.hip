@@ -194,7 +194,7 @@ __device__ __forceinline__ void slab_bin_octant(const Geom &g, uint32_t kbase, u
 // the same cycle) and moves in that octant's counts by device atomics.  dco_k:
 // the coordinates of domain k (kx | ky << 10 | kz << 20).
 __device__ __forceinline__ void slab_flip_part(const Geom &g, const uint32_t *o, uint32_t *sc, uint32_t dco_k,
-                                               uint32_t k, int so, uint32_t f, int part, long long &F,
+                                               const uint32_t *nb, uint32_t k, int so, uint32_t f, int part, long long &F,
                                                long long &dM, long long &dB) {
     const int cs = (int)(f >> 12);
     const uint32_t q = f & 0xFFFu;
@@ -202,7 +202,7 @@ __device__ __forceinline__ void slab_flip_part(const Geom &g, const uint32_t *o,
     const uint32_t up = cs >= 7;
     if (part == 0) {
         slab_move_lds(sc, cs, site_class(!up, up ? cs - 7 : 6 - cs), lz >> 2);
-        flip_site<16>(g, k, so, q);
+        flip_site<16>(g, k, so, q, nb);
         F += 1;
         dM += up ? -2 : 2;
         dB += 12 - 4 * (long long)(cs % 7);
@@ -577,7 +577,8 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
             const int part = tid & 3;
             const uint32_t f = ld < nvalid ? sh.selq[ld] : kNoEvent;
             if (f != kNoEvent)
-                slab_flip_part(g, sh.oct[ld], sh.sc[ld], sh.dco[ld], kbase + ld, s, f, part, myF, mydM, mydB);
+                slab_flip_part(g, sh.oct[ld], sh.sc[ld], sh.dco[ld], sh.nbdom[ld], kbase + ld, s, f, part, myF, mydM,
+                               mydB);
         }
         // this thread's flips and count moves complete (the flag below publishes them)
         if (publish_flag) __builtin_amdgcn_s_waitcnt(0);
@@ -850,7 +851,7 @@ __global__ void __launch_bounds__(kSlabBlock) k_srows_select(Geom g, uint64_t n)
         const int part = tid & 3;
         const uint32_t f = ld < rg.nvalid ? sh.selq[ld] : kNoEvent;
         if (f != kNoEvent)
-            slab_flip_part(g, sh.oct[ld], sh.sc[ld], sh.dco[ld], rg.dom(rg.kbase + ld), rg.oct(rg.kbase + ld, s), f,
+            slab_flip_part(g, sh.oct[ld], sh.sc[ld], sh.dco[ld], sh.nbdom[ld], rg.dom(rg.kbase + ld), rg.oct(rg.kbase + ld, s), f,
                            part, F, dM, dB);
     }
     __syncthreads();

@@ -132,29 +132,28 @@ __device__ __forceinline__ uint32_t dindex(int kx, int ky, int kz, int nd) {
 __device__ __forceinline__ int wrapm(int v, int nd) { return v == 0 ? nd - 1 : v - 1; }
 __device__ __forceinline__ int wrapp(int v, int nd) { return v + 1 == nd ? 0 : v + 1; }
 
-// The six halo faces of octant (k, s): for each axis the face of the octant of
-// colour s ^ (1 << axis) that touches it from below (x1/y1/z1 face) and from
-// above (x0/y0/z0 face).  nb holds the six neighbour domains of k
-// (-x, +x, -y, +y, -z, +z).
+// The six halo faces of octant (k, s): the layers of the octants of colour
+// s ^ (1 << axis) that touch it from below (their layer at local coordinate
+// h - 1) and from above (layer 0), kept by every octant as its own copy in F
+// (halo slots x below, x above, y below, y above, z below, z above; flips push
+// into them), so that an octant's halo is one contiguous 6 h^2 / 8 bytes.
 struct HaloFaces {
-    uint32_t lo[3];  // word index in F of the face at local coordinate h - 1 of the octant below
-    uint32_t hi[3];  // word index in F of the face at local coordinate 0 of the octant above
+    uint32_t lo[3];  // word index in F of the halo face below along each axis
+    uint32_t hi[3];  // word index in F of the halo face above
 };
 // (32-bit word indices from the uniform base: F holds K * 48 h^2 / 32 words,
 // below 2^31 for every supported size)
 template <int H>
-__device__ __forceinline__ HaloFaces halo_faces(uint32_t k, int s, const uint32_t *nb) {
+__device__ __forceinline__ HaloFaces halo_faces(uint32_t k, int s, const uint32_t *) {
     HaloFaces hf;
     constexpr uint32_t fw = H * H / 32, fwpo = 6 * fw;  // words per face, per octant
+    // domain indices stay below 2^22 (fewer than 2^34 sites, at least 4096 per
+    // domain): a 24-bit multiply
+    const uint32_t base = __umul24(k, 8u * fwpo) + (uint32_t)s * fwpo;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const int bit = (s >> a) & 1;
-        const uint32_t c = (uint32_t)(s ^ (1 << a));
-        const uint32_t kmi = bit ? k : nb[2 * a], kpi = bit ? nb[2 * a + 1] : k;  // below / above
-        // domain indices stay below 2^22 (fewer than 2^34 sites, at least 4096 per
-        // domain): a 24-bit multiply
-        hf.lo[a] = __umul24(kmi, 8u * fwpo) + c * fwpo + (uint32_t)(2 * a + 1) * fw;
-        hf.hi[a] = __umul24(kpi, 8u * fwpo) + c * fwpo + (uint32_t)(2 * a) * fw;
+        hf.lo[a] = base + (uint32_t)(2 * a) * fw;
+        hf.hi[a] = base + (uint32_t)(2 * a + 1) * fw;
     }
     return hf;
 }
@@ -598,20 +597,30 @@ __device__ __forceinline__ void select_site(const Planes<H> &pl, int cs, uint32_
     }
 }
 
-// Flip site q of octant (k, so): its spin word and the face copies it appears in.
+// Flip site q of octant (k, so): its spin word, and the halo copy of every
+// octant whose halo it is in (the octant across each of its octant's boundary
+// layers it lies on).  nb holds the six neighbour domains of k (-x, +x, -y,
+// +y, -z, +z).
 template <int H>
-__device__ __forceinline__ void flip_site(const Geom &g, uint32_t k, int so, uint32_t q) {
+__device__ __forceinline__ void flip_site(const Geom &g, uint32_t k, int so, uint32_t q, const uint32_t *nb) {
+    // 32-bit word indices: fewer than 2^34 sites (the spins' and the copies' words below 2^31)
     constexpr uint32_t wpo = H * H * H / 32, fwpo = 6 * H * H / 32;
-    flip_word(g.A + ((uint64_t)k * 8 + (uint32_t)so) * wpo + (q >> 5), 1u << (q & 31));
-    const uint32_t lx = q % H, ly = (q / H) % H, lz = q / (H * H);
-    uint32_t *F = g.F + ((uint64_t)k * 8 + (uint32_t)so) * fwpo;
-    constexpr uint32_t e = H - 1, h2 = H * H;
-    if (lx == 0) { uint32_t b = ly + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
-    if (lx == e) { uint32_t b = h2 + ly + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
-    if (ly == 0) { uint32_t b = 2 * h2 + lx + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
-    if (ly == e) { uint32_t b = 3 * h2 + lx + H * lz; flip_word(F + (b >> 5), 1u << (b & 31)); }
-    if (lz == 0) { uint32_t b = 4 * h2 + lx + H * ly; flip_word(F + (b >> 5), 1u << (b & 31)); }
-    if (lz == e) { uint32_t b = 5 * h2 + lx + H * ly; flip_word(F + (b >> 5), 1u << (b & 31)); }
+    flip_word(g.A + ((k * 8u + (uint32_t)so) * wpo + (q >> 5)), 1u << (q & 31));
+    const uint32_t c[3] = {q % H, (q / H) % H, q / (H * H)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (c[a] != 0 && c[a] != H - 1) continue;
+        // the site's place in a face: the other two coordinates, the lower axis first
+        const uint32_t u = a == 0 ? c[1] : c[0], v = a == 2 ? c[1] : c[2];
+        const uint32_t bit = u + H * v;
+        const bool below = c[a] == 0;  // layer 0: the halo above of the octant below
+        const bool inner = (((so >> a) & 1) != 0) == below;  // the octant across is in this domain
+        const uint32_t kt = inner ? k : nb[2 * a + (below ? 0 : 1)];
+        const uint32_t ot = (uint32_t)(so ^ (1 << a));
+        const uint32_t slot = (uint32_t)(2 * a + (below ? 1 : 0));
+        const uint32_t b = slot * H * H + bit;
+        flip_word(g.F + ((kt * 8u + ot) * fwpo + (b >> 5)), 1u << (b & 31));
+    }
 }
 
 // wall clock (100 MHz) for bounded waits

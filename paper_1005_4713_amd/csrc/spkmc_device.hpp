@@ -55,7 +55,8 @@ struct Geom {
     uint32_t *sc;          // PACKED, h = 16: per octant the class counts of its four 4-plane slabs (28 words)
     int8_t *spin8;         // INT8 spins
     uint32_t *A;           // PACKED spins, octant-major, canonical order inside an octant
-    uint32_t *F;           // PACKED face copies: per octant x0, x1, y0, y1, z0, z1 (h^2 bits each)
+    uint32_t *F;           // PACKED halo copies: per octant its halo faces x below, x above, y below,
+                           // y above, z below, z above (h^2 bits each)
     double r[14];          // rate table
     double rbound;         // R'_max = n_k max_c r_c (RMAX_BOUND)
     uint32_t lpd;          // frequency lines per domain and cycle: 1, or 4 (TWO_COLOURS)
