@@ -604,8 +604,14 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             mydB += 12 - 4 * (long long)(cs % 7);  // and its aligned count
         }
 
-        // this thread's flips complete (its only memory operations in flight)
-        __builtin_amdgcn_s_waitcnt(0);
+        // this thread's flips complete (its only memory operations in flight) when
+        // the next cycle reads what they changed: the same colour again (this
+        // workgroup reloads its octants) or a colour one bit away (neighbours wait for
+        // the flag).  Otherwise the next cycle's loads, issued after them, wait for
+        // them, which its R_max publish follows.
+        const int dn_next = s ^ s_next;
+        const bool indep = !INC && RND == 1 && !bound && lpd == 1 && n + 1 < n_end && (dn_next & (dn_next - 1)) != 0;
+        if (!indep) __builtin_amdgcn_s_waitcnt(0);
 
         // --- step 5: the clock, identical in every workgroup
         if (tid < 64) {
@@ -677,8 +683,10 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         if (tid == 0) {
             // the record partials stored above go out first; the flips are complete
             // (each thread waited for its own before the barrier)
-            if (record || last) __builtin_amdgcn_s_waitcnt(0);
-            st64(&xs.flag[gid], n + 1);
+            if (!indep) {
+                if (record || last) __builtin_amdgcn_s_waitcnt(0);
+                st64(&xs.flag[gid], n + 1);
+            }
         }
         if (bound && record && !last) {  // uniform over the workgroup
             if (recorder && tid < 64) {
