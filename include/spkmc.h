@@ -75,8 +75,9 @@ typedef enum spkmc_status {
 enum { SPKMC_RATES_GLAUBER = 0, SPKMC_RATES_METROPOLIS = 1 };
 enum { SPKMC_INIT_RANDOM = 0, SPKMC_INIT_UP = 1, SPKMC_INIT_DOWN = 2 };
 /* Spin storage in the device buffer.  INT8: one byte per site, index x + L (y + L z).
- * PACKED: one bit per site, octant-major (domain k, colour s, canonical q), plus a
- * copy of the 6 faces of every octant; needs h % 4 == 0. */
+ * PACKED: one bit per site, octant-major (domain k, colour s, canonical q), plus
+ * every octant's own copy of its halo (the 6 layers of the octants that touch it);
+ * needs h % 4 == 0. */
 enum { SPKMC_LAYOUT_INT8 = 0, SPKMC_LAYOUT_PACKED = 1 };
 /* Kernel engine.  AUTO picks PERSISTENT when supported (and when the domains
  * fit in one resident launch), else CYCLE.
