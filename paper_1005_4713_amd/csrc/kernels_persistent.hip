@@ -539,7 +539,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         // one thread per row with an event; incremental engine: three threads per
         // such row, one per axis, each moving the
         // classes of the flipped site's two neighbours along its axis; the first
-        // also flips the site (spin word and face copies) and moves its class
+        // also flips the site (spin word and halo copies) and moves its class
         const uint32_t nwork = INC ? 3 * D : D;
         for (uint32_t t = tid; t < nwork; t += nthr) {
             const uint32_t ld = INC ? t / 3 : t, ax = INC ? t % 3 : 0;
@@ -884,7 +884,7 @@ static void *select_kernel(int h, int P, int block, bool batch = false, bool inc
 bool persistent_supported(const Geom &g, const spkmc_params &p, bool inc, std::string &why) {
     if (g.layout != SPKMC_LAYOUT_PACKED) { why = "needs the PACKED layout"; return false; }
     if (g.h != 8 && g.h != 16) { why = "needs an octant edge of 8 or 16 (domain 16 or 32)"; return false; }
-    // spins and face copies are read through buffer views with 32-bit byte offsets
+    // spins and halo copies are read through buffer views with 32-bit byte offsets
     if (g.N / 8 >= (1ull << 31)) { why = "needs fewer than 2^34 sites"; return false; }
     const uint32_t ok = inc ? SPKMC_VARIANT_RMAX_ALL : (SPKMC_VARIANT_RMAX_BOUND | SPKMC_VARIANT_TWO_COLOURS);
     if (p.variant & ~ok) {

@@ -186,7 +186,7 @@ __device__ __forceinline__ void slab_bin_octant(const Geom &g, uint32_t kbase, u
 }
 
 // Part `part` of the flip f = (cs << 12) | q of octant (k, so): part 0 flips the
-// site (its spin word and face copies) and moves its class; parts 1..3 move the
+// site (its spin word and halo copies) and moves its class; parts 1..3 move the
 // classes of its two neighbours along axis part - 1.  A neighbour inside the
 // octant takes its class from the octant and halo in LDS (o; the flipped site
 // still reads its old spin there) and moves in the octant's counts in LDS (sc);
@@ -568,7 +568,7 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
         __syncthreads();
 
         // --- the flips: four threads per domain, the flipped site (and its spin
-        // word and face copies) and its two neighbours along each axis.  A
+        // word and halo copies) and its two neighbours along each axis.  A
         // neighbour inside the octant takes its class from the words in LDS (the
         // flipped site still reads its old spin there); one across a face reads
         // its own neighbours from memory (none of them flips in this cycle).

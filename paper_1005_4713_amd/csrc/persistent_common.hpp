@@ -3,7 +3,7 @@
 // launch-wide constants and descriptors, buffer views, v_bitop3 / DPP helpers,
 // the bit-sliced class planes of an octant (loads, neighbours, 6-input count,
 // popcount moments), the histogram from the moments, row scans and maxima, the
-// selection of a row's class and site, the flip of a site with its face copies,
+// selection of a row's class and site, the flip of a site with the halo copies it is in,
 // the bounded neighbour waits and the record sums of the persistent launches.
 #pragma once
 
@@ -54,7 +54,7 @@ __device__ __forceinline__ void st64(uint64_t *p, uint64_t v) {
 __device__ __forceinline__ uint64_t ld_words2(const uint32_t *p) {  // two consecutive words, 8-byte aligned
     return ld64(reinterpret_cast<const uint64_t *>(p));
 }
-// Buffer views of the packed spins and of the face copies (byte offsets below
+// Buffer views of the packed spins and of the halo copies (byte offsets below
 // 2^31 for every size the persistent engine takes), and the cache policy of a
 // device-coherent load (sc1).  A load at an offset past the end returns 0: the
 // rows of a pass without a line load there, so that every pass issues the same
@@ -73,7 +73,7 @@ __device__ __forceinline__ Views views_of(const Geom &g) {
     v.F = __builtin_amdgcn_make_buffer_rsrc((void *)g.F, (short)0, v.endF, 0x00020000);
     return v;
 }
-__device__ __forceinline__ uint32_t ld_face(const Views &v, bool valid, uint32_t w) {  // word w of the face copies
+__device__ __forceinline__ uint32_t ld_face(const Views &v, bool valid, uint32_t w) {  // word w of the halo copies
     return __builtin_amdgcn_raw_buffer_load_b32(v.F, valid ? (int)(w * 4u) : v.endF, 0, kCoherent);
 }
 __device__ __forceinline__ void flip_word(uint32_t *p, uint32_t m) {
@@ -269,7 +269,7 @@ __device__ __forceinline__ void load16_words(const Geom &g, uint32_t k, int s, b
         r.W[p + 3] = v[3];
     }
 }
-// The six halo faces: one 16-byte device-coherent load per lane (a face copy is
+// The six halo faces: one 16-byte device-coherent load per lane (a halo face is
 // 8 words at a 32-byte aligned address).
 __device__ __forceinline__ void load16_faces(const Geom &g, uint32_t k, int s, bool valid, int l, const uint32_t *nb,
                                              Raw<16> &r) {

@@ -41,7 +41,7 @@ struct Geom {
     uint64_t N;            // sites
     uint32_t h2, h3;       // h^2, h^3
     uint32_t wpo;          // PACKED: 32-bit words per octant (h^3 / 32)
-    uint32_t fwpo;         // PACKED: face words per octant (6 h^2 / 32)
+    uint32_t fwpo;         // PACKED: halo-copy words per octant (6 h^2 / 32)
     uint32_t rec_cap;
     uint32_t variant;      // SPKMC_VARIANT_* bits
     uint64_t seed;

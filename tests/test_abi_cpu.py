@@ -100,7 +100,7 @@ def test_rate_table_bitwise_equals_oracle(spkmc, rates, J, H, T):
 
 
 def test_state_bytes_scale(spkmc):
-    # packed 1024^3 with d = 32: bits of the spins, their face copies, the slab
+    # packed 1024^3 with d = 32: bits of the spins, their halo copies, the slab
     # engine's counts (896 bytes per domain) and per-domain scratch
     p = spkmc.make_params(1024, 32, layout="packed")
     nb = spkmc.state_bytes(p)
