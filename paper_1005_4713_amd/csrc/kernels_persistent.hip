@@ -139,6 +139,7 @@ __device__ __forceinline__ uint32_t row_lane(uint32_t v, int j) {
 template <int H, int P, int BLOCK, bool INC, int LPD, int RND = 1, class SH = PersistShared>
 __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t gid, SH &sh) {
     static_assert(RND == 1 || (!INC && P * RND <= 16), "the wide mode re-bins; a row's lanes draw for its lines");
+    static_assert(BLOCK >= 192, "the recorder sums records on its third wavefront");
     const Geom &g = R.g;
     const PersistScratch &xs = R.xs;
     const uint64_t n0 = R.n0, ncycles = R.ncycles;
@@ -160,6 +161,14 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     };
     const bool recorder = gid == 0;
     const uint64_t n_end = n0 + ncycles;
+
+    DevState *st = g.st;
+    // launch-start totals: during a launch only the recorder writes them, at
+    // its very end, after every workgroup has finished (read first, so that they
+    // travel with the predictions' read below)
+    const uint64_t fired0 = st->fired, nulls0 = st->nulls;
+    const int64_t M0 = st->M, B0 = st->B;
+    double t = st->t;  // every workgroup advances the same clock
 
     // neighbour workgroups per direction (0: -x, 1: +x, 2: -y, 3: +y, 4: -z, 5: +z)
     for (uint32_t i = tid; i < 6 * (kMaxGrid / 32); i += nthr) (&sh.nbr_bits[0][0])[i] = 0;
@@ -195,12 +204,6 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         for (int o = 0; o < 8; ++o) bin_all<H, P, BLOCK>(g, kbase, nvalid, o, sh);
     }
 
-    DevState *st = g.st;
-    // launch-start totals: during a launch only the recorder writes them, at
-    // its very end, after every workgroup has finished
-    const uint64_t fired0 = st->fired, nulls0 = st->nulls;
-    const int64_t M0 = st->M, B0 = st->B;
-    double t = st->t;  // every workgroup advances the same clock
     long long myF = 0, mydM = 0, mydB = 0;  // this thread's share since launch start
     uint32_t rec_index = 0;                  // records produced in this launch
     int prev_colour = -1;
@@ -451,10 +454,12 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             sh.next_lnu = -log(nd.ut);
         }
 
+        // workgroup 0 sums a record stored two or more cycles ago on its third
+        // wavefront, while the first polls
+        if (recorder && !bound && (tid >> 6) == 2 && sh.pend_head != sh.pend_tail &&
+            sh.pend_cycle[sh.pend_head % kRecBanks] + 2 <= n + 1)
+            emit_record<BLOCK == 1024 ? 1 : kWgPerLane>(g, xs, sh, G, tid & 63, n0, fired0, nulls0, M0, B0);
         if (tid < 64 && !bound) {
-            // workgroup 0 sums a record stored two or more cycles ago while it waits
-            if (recorder && sh.pend_head != sh.pend_tail && sh.pend_cycle[sh.pend_head % kRecBanks] + 2 <= n + 1)
-                emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
             // poll every slot until all carry this cycle's generation: one round of
             // loads for a block of slots, then only the ones not yet there
             uint64_t start = now_ticks();
@@ -692,19 +697,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             if (recorder && tid < 64) {
                 // fixed bound: workgroup 0 appends the record as soon as every
                 // workgroup has completed the cycle (its own flag is already out)
-                const uint64_t start = now_ticks();
-                bool ok = true;
-                for (uint32_t w = tid; w < G && ok; w += 64)
-                    while (ld64(&xs.flag[w]) < n + 1) {
-                        __builtin_amdgcn_s_sleep(1);
-                        if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
-                            atomicOr(&st->error, kErrFlagTimeout);
-                            sh.abort = 1;
-                            ok = false;
-                            break;
-                        }
-                    }
-                if (__all(ok)) {
+                if (wait_all_flags(xs, st, sh, G, tid, n + 1)) {
                     emit_record(g, xs, sh, G, tid, n0, fired0, nulls0, M0, B0);
                     if (tid == 0) st64(xs.emitted, (uint64_t)rec_index);
                 }
@@ -717,18 +710,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     // end of the launch: workgroup 0 waits for every workgroup to finish, then
     // appends the records still pending and the record of the last cycle
     if (recorder) {
-        if (tid < 64 && !sh.abort) {
-            uint64_t start = now_ticks();
-            for (uint32_t w = tid; w < G; w += 64)
-                while (ld64(&xs.flag[w]) < n_end) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
-                        atomicOr(&st->error, kErrFlagTimeout);
-                        sh.abort = 1;
-                        break;
-                    }
-                }
-        }
+        if (tid < 64 && !sh.abort) wait_all_flags(xs, st, sh, G, tid, n_end);
         __syncthreads();
         if (tid < 64 && !sh.abort) {
             while (sh.pend_head != sh.pend_tail) {

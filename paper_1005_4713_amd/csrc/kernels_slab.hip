@@ -660,18 +660,7 @@ __device__ __forceinline__ void slab_body(const Replica &R, const uint32_t gid, 
     // end of the launch: workgroup 0 waits for every workgroup, then appends the
     // pending records and the record of the last cycle
     if (recorder) {
-        if (tid < 64 && !sh.abort) {
-            uint64_t start = now_ticks();
-            for (uint32_t w = tid; w < G; w += 64)
-                while (ld64(&xs.flag[w]) < n_end) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
-                        atomicOr(&st->error, kErrFlagTimeout);
-                        sh.abort = 1;
-                        break;
-                    }
-                }
-        }
+        if (tid < 64 && !sh.abort) wait_all_flags(xs, st, sh, G, tid, n_end);
         __syncthreads();
         if (tid < 64 && !sh.abort) {
             while (sh.pend_head != sh.pend_tail) {

@@ -628,26 +628,92 @@ __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memr
 
 }  // namespace
 
-// Sum the partials of the oldest pending record over all workgroups (one
-// wavefront) and append the record.  The caller guarantees every workgroup has
-// stored them.
-template <class SH>
-__device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch &xs, SH &sh, uint32_t G,
-                                            int lane, uint64_t n0, uint64_t fired0, uint64_t nulls0, int64_t M0,
-                                            int64_t B0) {
-    const uint32_t slot = sh.pend_head % kRecBanks;
-    const int64_t *rp = xs.recp + (uint64_t)sh.pend_bank[slot] * G * 3;
-    long long F = 0, dM = 0, dB = 0;
-    for (uint32_t w = (uint32_t)lane; w < G; w += 64) {
-        F += (long long)ld64((const uint64_t *)&rp[3 * w]);
-        dM += (long long)ld64((const uint64_t *)&rp[3 * w + 1]);
-        dB += (long long)ld64((const uint64_t *)&rp[3 * w + 2]);
+// Sums over the workgroups of a launch, one wavefront: lane i takes workgroups
+// i, i + 64, ...  Each lane's loads for B workgroups go out together, so 64 B
+// workgroups cost one round trip (not one per load).
+constexpr int kWgPerLane = 4;
+
+// The (fired, dM, dB) triples p[3w .. 3w + 2] of workgroups w < G, summed over
+// the wavefront (every lane ends with the totals).
+template <int B = kWgPerLane>
+__device__ __forceinline__ void sum_triples(const int64_t *p, uint32_t G, int lane, long long &F, long long &dM,
+                                            long long &dB) {
+    F = dM = dB = 0;
+    for (uint32_t base = 0; base < G; base += 64 * B) {
+        uint64_t v[B][3];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const uint32_t w = base + (uint32_t)(i * 64 + lane);
+            const uint32_t wc = w < G ? w : G - 1;  // lanes past the end read a valid word and drop it
+#pragma unroll
+            for (int j = 0; j < 3; ++j) v[i][j] = ld64(reinterpret_cast<const uint64_t *>(&p[3 * wc + j]));
+        }
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            if (base + (uint32_t)(i * 64 + lane) < G) {
+                F += (long long)v[i][0];
+                dM += (long long)v[i][1];
+                dB += (long long)v[i][2];
+            }
     }
     for (int o = 32; o > 0; o >>= 1) {
         F += __shfl_xor(F, o);
         dM += __shfl_xor(dM, o);
         dB += __shfl_xor(dB, o);
     }
+}
+
+// Wait (one wavefront) until every workgroup's flag has reached `upto`; only
+// the flags not yet there are read again.  false on a timeout or a device
+// error (error set, sh.abort raised).
+template <class SH>
+__device__ __forceinline__ bool wait_all_flags(const PersistScratch &xs, DevState *st, SH &sh, uint32_t G,
+                                               int lane, uint64_t upto) {
+    const uint64_t start = now_ticks();
+    for (uint32_t base = 0; base < G; base += 64 * kWgPerLane) {
+        uint64_t fv[kWgPerLane];
+#pragma unroll
+        for (int i = 0; i < kWgPerLane; ++i) {
+            const uint32_t w = base + (uint32_t)(i * 64 + lane);
+            fv[i] = w < G ? ld64(&xs.flag[w]) : upto;
+        }
+        for (;;) {
+            bool done = true;
+#pragma unroll
+            for (int i = 0; i < kWgPerLane; ++i)
+                if (fv[i] < upto) {
+                    done = false;
+                    fv[i] = ld64(&xs.flag[base + (uint32_t)(i * 64 + lane)]);
+                }
+            if (__all(done)) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
+                atomicOr(&st->error, kErrFlagTimeout);
+                sh.abort = 1;
+                return false;
+            }
+        }
+    }
+    return true;
+}
+
+// Sum the partials of the oldest pending record over all workgroups (one
+// wavefront) and append the record.  The caller guarantees every workgroup has
+// stored them.  B: workgroups per lane and round trip (fewer where registers
+// are scarce).
+template <int B = kWgPerLane, class SH>
+__device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch &xs, SH &sh, uint32_t G,
+                                            int lane, uint64_t n0, uint64_t fired0, uint64_t nulls0, int64_t M0,
+                                            int64_t B0) {
+    const uint32_t slot = sh.pend_head % kRecBanks;
+    const int64_t *rp = xs.recp + (uint64_t)sh.pend_bank[slot] * G * 3;
+    DevState *st = g.st;
+    // the ring index, in flight with the partials (a per-lane value: read as a
+    // uniform one it would be waited for at once); only the recorder writes it
+    uint64_t rc = 0;
+    if (lane == 0) rc = ld64(&st->rec_count);
+    long long F, dM, dB;
+    sum_triples<B>(rp, G, lane, F, dM, dB);
     if (lane == 0) {
         const uint64_t cyc = sh.pend_cycle[slot];
         spkmc_record r;
@@ -657,9 +723,8 @@ __device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch 
         r.t = sh.pend_t[slot];
         r.M = M0 + dM;
         r.B = B0 + dB;
-        DevState *st = g.st;
-        g.rec[st->rec_count % g.rec_cap] = r;
-        st->rec_count += 1;
+        g.rec[rc % g.rec_cap] = r;
+        st->rec_count = rc + 1;
         sh.pend_head += 1;
     }
 }
@@ -670,19 +735,28 @@ template <int BLOCK, class SH>
 __device__ __forceinline__ bool wait_neighbours(const PersistScratch &xs, DevState *st, SH &sh, uint32_t G,
                                                 int dir, uint64_t upto) {
     const int tid = threadIdx.x;
-    for (int d = dir < 0 ? 0 : dir; d < (dir < 0 ? 6 : dir + 1); ++d) {
-        const bool all = sh.nbr_cnt[d] > kMaxNbr;
-        const uint32_t cnt = all ? G : sh.nbr_cnt[d];
-        for (uint32_t i = tid; i < cnt; i += BLOCK) {
-            const uint32_t w = all ? i : sh.nbr[d][i];
-            const uint64_t start = now_ticks();
-            while (ld64(&xs.flag[w]) < upto) {
-                __builtin_amdgcn_s_sleep(1);
-                if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
-                    atomicOr(&st->error, kErrFlagTimeout);
-                    sh.abort = 1;
-                    break;
-                }
+    // the directions' lists laid end to end, one flag per thread: every thread
+    // waits on its own flag, so all directions cost one round trip together
+    const int d0 = dir < 0 ? 0 : dir, d1 = dir < 0 ? 6 : dir + 1;
+    uint32_t total = 0;
+    for (int d = d0; d < d1; ++d) total += sh.nbr_cnt[d] > kMaxNbr ? G : sh.nbr_cnt[d];
+    for (uint32_t j = tid; j < total; j += BLOCK) {
+        uint32_t i = j;
+        int d = d0;
+        for (;;) {
+            const uint32_t cnt = sh.nbr_cnt[d] > kMaxNbr ? G : sh.nbr_cnt[d];
+            if (i < cnt) break;
+            i -= cnt;
+            ++d;
+        }
+        const uint32_t w = sh.nbr_cnt[d] > kMaxNbr ? i : sh.nbr[d][i];
+        const uint64_t start = now_ticks();
+        while (ld64(&xs.flag[w]) < upto) {
+            __builtin_amdgcn_s_sleep(1);
+            if (now_ticks() - start > kTimeoutTicks || ld32(&st->error)) {
+                atomicOr(&st->error, kErrFlagTimeout);
+                sh.abort = 1;
+                break;
             }
         }
     }
@@ -773,17 +847,8 @@ __device__ __forceinline__ void store_final(const PersistScratch &xs, uint32_t g
 template <class SH>
 __device__ __forceinline__ void fold_final(const Geom &g, const PersistScratch &xs, SH &sh, uint32_t G, int lane,
                                            uint64_t NLc, uint64_t fired0, uint64_t nulls0, int64_t M0, int64_t B0) {
-    long long F = 0, dM = 0, dB = 0;
-    for (uint32_t w = (uint32_t)lane; w < G; w += 64) {
-        F += (long long)ld64(reinterpret_cast<const uint64_t *>(&xs.fin[3 * w]));
-        dM += (long long)ld64(reinterpret_cast<const uint64_t *>(&xs.fin[3 * w + 1]));
-        dB += (long long)ld64(reinterpret_cast<const uint64_t *>(&xs.fin[3 * w + 2]));
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        F += __shfl_xor(F, o);
-        dM += __shfl_xor(dM, o);
-        dB += __shfl_xor(dB, o);
-    }
+    long long F, dM, dB;
+    sum_triples(xs.fin, G, lane, F, dM, dB);
     if (lane < 8) xs.rpred[lane] = sh.rpred[lane];
     if (lane == 0) {
         DevState *st = g.st;
