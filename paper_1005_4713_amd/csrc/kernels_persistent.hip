@@ -458,7 +458,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         // wavefront, while the first polls
         if (recorder && !bound && (tid >> 6) == 2 && sh.pend_head != sh.pend_tail &&
             sh.pend_cycle[sh.pend_head % kRecBanks] + 2 <= n + 1)
-            emit_record<BLOCK == 1024 ? 1 : kWgPerLane>(g, xs, sh, G, tid & 63, n0, fired0, nulls0, M0, B0);
+            emit_record(g, xs, sh, G, tid & 63, n0, fired0, nulls0, M0, B0);
         if (tid < 64 && !bound) {
             // poll every slot until all carry this cycle's generation: one round of
             // loads for a block of slots, then only the ones not yet there

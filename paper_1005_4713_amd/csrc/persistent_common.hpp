@@ -628,28 +628,27 @@ __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memr
 
 }  // namespace
 
-// Sums over the workgroups of a launch, one wavefront: lane i takes workgroups
-// i, i + 64, ...  Each lane's loads for B workgroups go out together, so 64 B
-// workgroups cost one round trip (not one per load).
+// Sums and waits over the workgroups of a launch at its end, one wavefront: lane
+// i takes workgroups i, i + 64, ...  Each lane's loads for kWgPerLane workgroups
+// go out together, so 256 workgroups cost one round trip (not one per load).
 constexpr int kWgPerLane = 4;
 
 // The (fired, dM, dB) triples p[3w .. 3w + 2] of workgroups w < G, summed over
 // the wavefront (every lane ends with the totals).
-template <int B = kWgPerLane>
 __device__ __forceinline__ void sum_triples(const int64_t *p, uint32_t G, int lane, long long &F, long long &dM,
                                             long long &dB) {
     F = dM = dB = 0;
-    for (uint32_t base = 0; base < G; base += 64 * B) {
-        uint64_t v[B][3];
+    for (uint32_t base = 0; base < G; base += 64 * kWgPerLane) {
+        uint64_t v[kWgPerLane][3];
 #pragma unroll
-        for (int i = 0; i < B; ++i) {
+        for (int i = 0; i < kWgPerLane; ++i) {
             const uint32_t w = base + (uint32_t)(i * 64 + lane);
             const uint32_t wc = w < G ? w : G - 1;  // lanes past the end read a valid word and drop it
 #pragma unroll
             for (int j = 0; j < 3; ++j) v[i][j] = ld64(reinterpret_cast<const uint64_t *>(&p[3 * wc + j]));
         }
 #pragma unroll
-        for (int i = 0; i < B; ++i)
+        for (int i = 0; i < kWgPerLane; ++i)
             if (base + (uint32_t)(i * 64 + lane) < G) {
                 F += (long long)v[i][0];
                 dM += (long long)v[i][1];
@@ -699,21 +698,26 @@ __device__ __forceinline__ bool wait_all_flags(const PersistScratch &xs, DevStat
 
 // Sum the partials of the oldest pending record over all workgroups (one
 // wavefront) and append the record.  The caller guarantees every workgroup has
-// stored them.  B: workgroups per lane and round trip (fewer where registers
-// are scarce).
-template <int B = kWgPerLane, class SH>
+// stored them.  (A lane's loads are not batched here as in sum_triples: inside
+// the main loop that code slowed the cycle of the batch kernels by a tenth and
+// the single-lattice cycle by 1 %, even in launches that emit no record.)
+template <class SH>
 __device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch &xs, SH &sh, uint32_t G,
                                             int lane, uint64_t n0, uint64_t fired0, uint64_t nulls0, int64_t M0,
                                             int64_t B0) {
     const uint32_t slot = sh.pend_head % kRecBanks;
     const int64_t *rp = xs.recp + (uint64_t)sh.pend_bank[slot] * G * 3;
-    DevState *st = g.st;
-    // the ring index, in flight with the partials (a per-lane value: read as a
-    // uniform one it would be waited for at once); only the recorder writes it
-    uint64_t rc = 0;
-    if (lane == 0) rc = ld64(&st->rec_count);
-    long long F, dM, dB;
-    sum_triples<B>(rp, G, lane, F, dM, dB);
+    long long F = 0, dM = 0, dB = 0;
+    for (uint32_t w = (uint32_t)lane; w < G; w += 64) {
+        F += (long long)ld64((const uint64_t *)&rp[3 * w]);
+        dM += (long long)ld64((const uint64_t *)&rp[3 * w + 1]);
+        dB += (long long)ld64((const uint64_t *)&rp[3 * w + 2]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        F += __shfl_xor(F, o);
+        dM += __shfl_xor(dM, o);
+        dB += __shfl_xor(dB, o);
+    }
     if (lane == 0) {
         const uint64_t cyc = sh.pend_cycle[slot];
         spkmc_record r;
@@ -723,8 +727,9 @@ __device__ __forceinline__ void emit_record(const Geom &g, const PersistScratch 
         r.t = sh.pend_t[slot];
         r.M = M0 + dM;
         r.B = B0 + dB;
-        g.rec[rc % g.rec_cap] = r;
-        st->rec_count = rc + 1;
+        DevState *st = g.st;
+        g.rec[st->rec_count % g.rec_cap] = r;
+        st->rec_count += 1;
         sh.pend_head += 1;
     }
 }
