@@ -545,10 +545,11 @@ def main():
     inc = info["engine"] == spkmc.ENGINES["incremental"]
     lpd = 4 if sim.params.variant & spkmc.VARIANTS["two_colours"] else 1
     passes = info["wg_domains"] * 16 // info["block"] if info["block"] else 0
+    bnd = int(bool(sim.params.variant & spkmc.VARIANTS["rmax_bound"]) and not inc)  # the bound compiled in
     kernel = (f"k_persistent<{info['h']}, {passes}, {info['block']}, "
-              f"{str(inc).lower()}, {lpd}>" if launches == 1 else "whole cycle (3 launches)")
+              f"{str(inc).lower()}, {lpd}, {bnd}>" if launches == 1 else "whole cycle (3 launches)")
     if launches == 1 and passes > 4:  # the wide mode: rounds of four passes
-        kernel = f"k_persistent_wide<{passes // 4}, {lpd}>"
+        kernel = f"k_persistent_wide<{passes // 4}, {lpd}, {bnd}>"
     if info["engine"] == spkmc.ENGINES["slab"]:
         kernel = f"k_slab<{str(bool(sim.params.variant & spkmc.VARIANTS['rmax_all'])).lower()}>"
     traffic, traffic_rec = (None, None)

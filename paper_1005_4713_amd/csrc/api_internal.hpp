@@ -36,8 +36,9 @@ hipError_t launch_slab(const Geom &g, uint64_t n0, uint64_t ncycles, uint32_t ob
                        hipStream_t stream);
 struct Replica;
 size_t replica_bytes();
-// lpd: 1 when every lattice has one line per domain (eight colours; a kernel
-// with that fixed at compile time), 0 otherwise
+// lpd: 1 when every lattice has one line per domain (eight colours) and none
+// runs with the fixed bound (a kernel with both fixed at compile time), 0
+// otherwise
 hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t *ncycles, uint32_t obs_every,
                       uint32_t n, int P, Replica *out, int &grid, int &block, uint32_t &lpd);
 hipError_t upload_replicas(const Replica *host, uint32_t n, Replica *dev, hipStream_t stream);

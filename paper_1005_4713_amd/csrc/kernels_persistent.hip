@@ -136,7 +136,10 @@ __device__ __forceinline__ uint32_t row_lane(uint32_t v, int j) {
 // RND > 1 (the wide mode, re-binning engine only): each row runs RND rounds of P
 // lines; the bin keeps only their moments, the selection waits for the true
 // R_max and derives every round's class planes again from the spins.
-template <int H, int P, int BLOCK, bool INC, int LPD, int RND = 1, class SH = PersistShared>
+// BND: 1 when the lattice may run with the fixed bound (read from the variant at
+// run time), 0 when it does not (the bound's code is compiled out: present in the
+// loop without running, it still slowed the cycle by about 1.5 %).
+template <int H, int P, int BLOCK, bool INC, int LPD, int BND, int RND = 1, class SH = PersistShared>
 __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t gid, SH &sh) {
     static_assert(RND == 1 || (!INC && P * RND <= 16), "the wide mode re-bins; a row's lanes draw for its lines");
     static_assert(BLOCK >= 192, "the recorder sums records on its third wavefront");
@@ -207,7 +210,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
     long long myF = 0, mydM = 0, mydB = 0;  // this thread's share since launch start
     uint32_t rec_index = 0;                  // records produced in this launch
     int prev_colour = -1;
-    const bool bound = (g.variant & SPKMC_VARIANT_RMAX_BOUND) != 0;   // re-binning engine only
+    const bool bound = BND != 0 && (g.variant & SPKMC_VARIANT_RMAX_BOUND) != 0;  // re-binning engine only
     // the bound as a value: a conditional read of it or of an LDS word would be a
     // generic (flat) load, whose wait also waits for this wavefront's slot store
     const double rbound = g.rbound;
@@ -739,24 +742,25 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
 
 // One lattice: the descriptor by value; LPD, the frequency lines per domain (1
 // or 4), fixed at compile time so that every line of a pass shares its octant.
-template <int H, int P, int BLOCK, bool INC, int LPD>
+template <int H, int P, int BLOCK, bool INC, int LPD, int BND>
 __global__ void __launch_bounds__(BLOCK) k_persistent(Replica R) {
     __shared__ PersistShared sh;
-    persistent_body<H, P, BLOCK, INC, LPD>(R, blockIdx.x, sh);
+    persistent_body<H, P, BLOCK, INC, LPD, BND>(R, blockIdx.x, sh);
 }
 
 // One lattice in the wide mode (octant edge 16; RND rounds of four passes, 128 RND
 // lines per workgroup).
-template <int RND, int LPD>
+template <int RND, int LPD, int BND>
 __global__ void __launch_bounds__(512) k_persistent_wide(Replica R) {
     __shared__ PersistSharedWide<RND> sh;
-    persistent_body<16, 4, 512, false, LPD, RND, PersistSharedWide<RND>>(R, blockIdx.x, sh);
+    persistent_body<16, 4, 512, false, LPD, BND, RND, PersistSharedWide<RND>>(R, blockIdx.x, sh);
 }
 
 // Many independent lattices in one launch: each workgroup finds its lattice by
 // its workgroup index; lattices never wait for one another.
 // LPD: 1 when every lattice of the batch has eight colours (one line per domain,
-// fixed at compile time), 0 for batches that mix in two-colour lattices.
+// fixed at compile time) and none the fixed bound; 0 for batches that mix in
+// two-colour or fixed-bound lattices (both read at run time).
 template <int H, int P, int BLOCK, bool INC, int LPD>
 __global__ void __launch_bounds__(BLOCK) k_persistent_batch(const Replica *__restrict__ reps, uint32_t nrep) {
     __shared__ PersistShared sh;
@@ -769,7 +773,7 @@ __global__ void __launch_bounds__(BLOCK) k_persistent_batch(const Replica *__res
     // the index is the same in every lane: keep the descriptor in scalar registers
     const Replica &R = reps[__builtin_amdgcn_readfirstlane(lo)];
     if (blockIdx.x >= R.first_wg + R.G) return;  // a spare workgroup past the last lattice
-    persistent_body<H, P, BLOCK, INC, LPD>(R, blockIdx.x - R.first_wg, sh);
+    persistent_body<H, P, BLOCK, INC, LPD, LPD == 0 ? 1 : 0>(R, blockIdx.x - R.first_wg, sh);
 }
 
 // Before a launch: slots carry the generation of no cycle of this launch yet,
@@ -817,17 +821,22 @@ int batch_max_passes(int h) { return h == 8 ? 2 : 4; }
 
 // batch: lpd = 1 (every lattice with eight colours) or 0 (lines per domain read
 // at run time)
+// bnd: the lattice runs with the fixed bound (single lattices; a batch's lpd
+// covers it).
 template <int H, int P, int BLOCK>
-static void *kernel_of(bool batch, bool inc, uint32_t lpd) {
+static void *kernel_of(bool batch, bool inc, uint32_t lpd, bool bnd) {
     if (inc) {
-        if constexpr (P <= 2 && BLOCK == 512) return reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, true, 1>);
+        if constexpr (P <= 2 && BLOCK == 512) return reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, true, 1, 0>);
         return nullptr;
     }
     if (batch)
         return lpd == 1 ? reinterpret_cast<void *>(&k_persistent_batch<H, P, BLOCK, false, 1>)
                         : reinterpret_cast<void *>(&k_persistent_batch<H, P, BLOCK, false, 0>);
-    return lpd == 4 ? reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false, 4>)
-                    : reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false, 1>);
+    if (bnd)
+        return lpd == 4 ? reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false, 4, 1>)
+                        : reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false, 1, 1>);
+    return lpd == 4 ? reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false, 4, 0>)
+                    : reinterpret_cast<void *>(&k_persistent<H, P, BLOCK, false, 1, 0>);
 }
 
 // The wide mode's rounds for one lattice: 1 (passes only), 2 or 4 (octant edge 16,
@@ -835,31 +844,40 @@ static void *kernel_of(bool batch, bool inc, uint32_t lpd) {
 static int max_rounds(int h, bool inc) { return h == 16 && !inc ? 4 : 1; }
 
 // Batches use the re-binning kernel (lines per domain read at run time).
+static bool has_bound(const Geom &g) { return (g.variant & SPKMC_VARIANT_RMAX_BOUND) != 0; }
+
+template <int RND>
+static void *wide_kernel(uint32_t lpd, bool bnd) {
+    if (bnd)
+        return lpd == 4 ? reinterpret_cast<void *>(&k_persistent_wide<RND, 4, 1>)
+                        : reinterpret_cast<void *>(&k_persistent_wide<RND, 1, 1>);
+    return lpd == 4 ? reinterpret_cast<void *>(&k_persistent_wide<RND, 4, 0>)
+                    : reinterpret_cast<void *>(&k_persistent_wide<RND, 1, 0>);
+}
+
 static void *select_kernel(int h, int P, int block, bool batch = false, bool inc = false, uint32_t lpd = 1,
-                           int rnd = 1) {
+                           int rnd = 1, bool bnd = false) {
     if (batch && inc) return nullptr;
     if (rnd > 1) {
         if (batch || inc || h != 16 || block != 512 || P != 4) return nullptr;
-        if (rnd == 2)
-            return lpd == 4 ? reinterpret_cast<void *>(&k_persistent_wide<2, 4>)
-                            : reinterpret_cast<void *>(&k_persistent_wide<2, 1>);
-        if (rnd == 4)
-            return lpd == 4 ? reinterpret_cast<void *>(&k_persistent_wide<4, 4>)
-                            : reinterpret_cast<void *>(&k_persistent_wide<4, 1>);
+        if (rnd == 2) return wide_kernel<2>(lpd, bnd);
+        if (rnd == 4) return wide_kernel<4>(lpd, bnd);
         return nullptr;
     }
     if (h == 16 && block == 512)
-        return P == 1   ? kernel_of<16, 1, 512>(batch, inc, lpd)
-               : P == 2 ? kernel_of<16, 2, 512>(batch, inc, lpd)
-               : P == 4 ? kernel_of<16, 4, 512>(batch, inc, lpd)
+        return P == 1   ? kernel_of<16, 1, 512>(batch, inc, lpd, bnd)
+               : P == 2 ? kernel_of<16, 2, 512>(batch, inc, lpd, bnd)
+               : P == 4 ? kernel_of<16, 4, 512>(batch, inc, lpd, bnd)
                         : nullptr;
     if (h == 8 && block == 1024 && !inc)
-        return P == 1   ? kernel_of<8, 1, 1024>(batch, inc, lpd)
-               : P == 2 ? kernel_of<8, 2, 1024>(batch, inc, lpd)
-               : P == 4 ? kernel_of<8, 4, 1024>(batch, inc, lpd)
+        return P == 1   ? kernel_of<8, 1, 1024>(batch, inc, lpd, bnd)
+               : P == 2 ? kernel_of<8, 2, 1024>(batch, inc, lpd, bnd)
+               : P == 4 ? kernel_of<8, 4, 1024>(batch, inc, lpd, bnd)
                         : nullptr;
     if (h == 8 && block == 512 && inc && !batch)
-        return P == 1 ? kernel_of<8, 1, 512>(false, true, 1) : P == 2 ? kernel_of<8, 2, 512>(false, true, 1) : nullptr;
+        return P == 1   ? kernel_of<8, 1, 512>(false, true, 1, false)
+               : P == 2 ? kernel_of<8, 2, 512>(false, true, 1, false)
+                        : nullptr;
     return nullptr;
 }
 
@@ -899,7 +917,7 @@ hipError_t persistent_configure(const Geom &g, const spkmc_params &p, bool inc, 
     for (int pc = 1; pc <= pmax * max_rounds(g.h, inc); pc <<= 1) {
         const int P = pc < pmax ? pc : pmax;
         if (p.wg_domains && p.wg_domains != rows * pc) continue;
-        void *kern = select_kernel(g.h, P, block, false, inc, g.lpd, pc / P);
+        void *kern = select_kernel(g.h, P, block, false, inc, g.lpd, pc / P, has_bound(g));
         if (!kern) return hipErrorInvalidValue;
         int occ = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, 0);
@@ -931,7 +949,7 @@ hipError_t launch_persistent(const Geom &g, uint64_t n0, uint64_t ncycles, uint3
                              int wg_domains, bool inc, bool prep, hipStream_t stream) {
     PersistScratch xs = scratch_of(g, grid);
     const int pc = wg_domains / (block / 16), P = pc < 4 ? pc : 4;  // passes, then rounds of four passes
-    void *kern = select_kernel(g.h, P, block, false, inc, g.lpd, pc / P);
+    void *kern = select_kernel(g.h, P, block, false, inc, g.lpd, pc / P, has_bound(g));
     if (!kern) return hipErrorInvalidValue;
     if (prep || inc) {  // the incremental engine clears its pushed class changes every launch
         const uint64_t ndh = inc ? (uint64_t)g.K * 16 : 0;
@@ -994,7 +1012,7 @@ hipError_t batch_plan(const Geom *const *gs, const uint64_t *n0, const uint64_t 
     block = persist_rows(h, false) * 16;
     lpd = 1;
     for (uint32_t i = 0; i < n; ++i)
-        if (gs[i]->lpd != 1) lpd = 0;
+        if (gs[i]->lpd != 1 || has_bound(*gs[i])) lpd = 0;
     void *kern = select_kernel(h, P, block, true, false, lpd);
     if (!kern) return hipErrorInvalidValue;
     uint32_t first = 0;
