@@ -819,10 +819,9 @@ int persist_max_passes(int, bool inc) { return inc ? 2 : 4; }
 // with four the batch kernel's run-time descriptor spills registers.
 int batch_max_passes(int h) { return h == 8 ? 2 : 4; }
 
-// batch: lpd = 1 (every lattice with eight colours) or 0 (lines per domain read
-// at run time)
-// bnd: the lattice runs with the fixed bound (single lattices; a batch's lpd
-// covers it).
+// batch: lpd = 1 (every lattice with eight colours and without the fixed bound)
+// or 0 (lines per domain and the bound read at run time).  Single lattices: bnd,
+// the lattice runs with the fixed bound.
 template <int H, int P, int BLOCK>
 static void *kernel_of(bool batch, bool inc, uint32_t lpd, bool bnd) {
     if (inc) {
@@ -843,7 +842,6 @@ static void *kernel_of(bool batch, bool inc, uint32_t lpd, bool bnd) {
 // re-binning engine).
 static int max_rounds(int h, bool inc) { return h == 16 && !inc ? 4 : 1; }
 
-// Batches use the re-binning kernel (lines per domain read at run time).
 static bool has_bound(const Geom &g) { return (g.variant & SPKMC_VARIANT_RMAX_BOUND) != 0; }
 
 template <int RND>
@@ -855,6 +853,7 @@ static void *wide_kernel(uint32_t lpd, bool bnd) {
                     : reinterpret_cast<void *>(&k_persistent_wide<RND, 1, 0>);
 }
 
+// Batches use the re-binning kernel (see kernel_of for lpd and bnd).
 static void *select_kernel(int h, int P, int block, bool batch = false, bool inc = false, uint32_t lpd = 1,
                            int rnd = 1, bool bnd = false) {
     if (batch && inc) return nullptr;
