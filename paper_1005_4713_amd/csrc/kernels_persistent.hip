@@ -47,6 +47,7 @@
 // Every wait is bounded in wall-clock time; a timeout sets DevState::error and
 // every workgroup leaves the loop.
 #include <mutex>
+#include <type_traits>
 #include <string>
 
 #include "persistent_common.hpp"
@@ -54,11 +55,13 @@
 namespace spkmc {
 
 // Workgroup-shared state of the persistent kernel for up to DMAX frequency lines
-// (HISTP: with the incremental engine's packed counts of all eight octants).
-template <uint32_t DMAX, bool HISTP>
+// (HISTP: with the incremental engine's packed counts of all eight octants; MW:
+// moment words per line, 13 totals, or 32 for the one-round kernels' partial
+// sums of four groups of four lanes, seven packed words and a spare each).
+template <uint32_t DMAX, bool HISTP, int MW>
 struct PersistSharedT {
     double r[14];               // rate table
-    uint32_t mom[DMAX][13];     // per line: the 13 popcount moments of its active octant
+    alignas(16) uint32_t mom[DMAX][MW];  // per line: the popcount moments of its active octant
     uint32_t hist[DMAX][14];    // per line: class histogram (re-binning engine)
     uint32_t histp[HISTP ? DMAX : 1][8][7];  // per domain and octant: packed class counts (incremental engine)
     double acc[DMAX][14];       // per line: running FP64 sums of the frequency line
@@ -81,17 +84,20 @@ struct PersistSharedT {
     double pend_t[kRecBanks];
     uint32_t pend_bank[kRecBanks];
 };
-using PersistShared = PersistSharedT<kMaxWgDomains, true>;
+// The one-round re-binning kernels, and the incremental engine's (totals kept
+// per line, and every octant's counts).
+using PersistShared = PersistSharedT<kMaxWgDomains, false, 32>;
+using PersistSharedInc = PersistSharedT<kMaxWgDomains, true, 13>;
 // The wide mode (octant edge 16): RND = 2 or 4 rounds of four passes of 32 rows,
 // 256 or 512 lines per workgroup.
 template <int RND>
-using PersistSharedWide = PersistSharedT<32 * 4 * RND, false>;
+using PersistSharedWide = PersistSharedT<32 * 4 * RND, false, 13>;
 static_assert(sizeof(PersistSharedWide<4>) <= 160 * 1024, "wide-mode LDS exceeds a CU's 160 KB");
 
 // Bin octant o of every domain of the workgroup (the 13 moments of each row, then
 // its histogram) into the packed counts of that octant.
 template <int H, int P, int BLOCK>
-__device__ __forceinline__ void bin_all(const Geom &g, uint32_t kbase, uint32_t nvalid, int o, PersistShared &sh) {
+__device__ __forceinline__ void bin_all(const Geom &g, uint32_t kbase, uint32_t nvalid, int o, PersistSharedInc &sh) {
     constexpr int rows = BLOCK / 16;
     const int tid = threadIdx.x, row = tid >> 4, l = tid & 15;
     constexpr uint32_t D = (uint32_t)(rows * P);
@@ -139,7 +145,8 @@ __device__ __forceinline__ uint32_t row_lane(uint32_t v, int j) {
 // BND: 1 when the lattice may run with the fixed bound (read from the variant at
 // run time), 0 when it does not (the bound's code is compiled out: present in the
 // loop without running, it still slowed the cycle by about 1.5 %).
-template <int H, int P, int BLOCK, bool INC, int LPD, int BND, int RND = 1, class SH = PersistShared>
+template <int H, int P, int BLOCK, bool INC, int LPD, int BND, int RND = 1,
+          class SH = std::conditional_t<INC, PersistSharedInc, PersistShared>>
 __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t gid, SH &sh) {
     static_assert(RND == 1 || (!INC && P * RND <= 16), "the wide mode re-bins; a row's lanes draw for its lines");
     static_assert(BLOCK >= 192, "the recorder sums records on its third wavefront");
@@ -362,26 +369,34 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
 #pragma unroll
                 for (int i = 0; i < 13; ++i) m[i] = 0;
                 compute_octant<H, true>(raw[pp], valid, l, sh.zbuf[row], pl[pp], m);
-                // row totals (at most h^3 <= 4096 each), two to a word for the scan
+                // sums over groups of four lanes (two DPP steps; the last lane of a
+                // group holds its group's), two moments to a word (at most h^3 <=
+                // 4096 each); the histogram adds the four groups
                 uint32_t mp[7];
 #pragma unroll
-                for (int i = 0; i < 6; ++i) mp[i] = row_scan(m[2 * i] | (m[2 * i + 1] << 16));
-                mp[6] = row_scan(m[12]);
-                if (l == 15) {
-#pragma unroll
-                    for (int i = 0; i < 6; ++i) {
-                        sh.mom[ld][2 * i] = mp[i] & 0xFFFFu;
-                        sh.mom[ld][2 * i + 1] = mp[i] >> 16;
-                    }
-                    sh.mom[ld][12] = mp[6];
+                for (int i = 0; i < 6; ++i) mp[i] = quad_sum(m[2 * i] | (m[2 * i + 1] << 16));
+                mp[6] = quad_sum(m[12]);
+                if ((l & 3) == 3) {
+                    uint32_t *dst = &sh.mom[ld][8 * (l >> 2)];
+                    *reinterpret_cast<uint4 *>(dst) = uint4{mp[0], mp[1], mp[2], mp[3]};
+                    *reinterpret_cast<uint4 *>(dst + 4) = uint4{mp[4], mp[5], mp[6], 0u};
                 }
             }
             __syncthreads();
             // step 1: histogram and frequency line of every domain of the workgroup,
             // running sums kept for the selection (the same sums in the same order)
             for (uint32_t i = tid; i < D; i += nthr) {
-                uint32_t mm[13], hc[14];
-                for (int c = 0; c < 13; ++c) mm[c] = sh.mom[i][c];
+                uint32_t mm[13], hc[14], w[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) w[c] += sh.mom[i][8 * q + c];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    mm[2 * c] = w[c] & 0xFFFFu;
+                    mm[2 * c + 1] = w[c] >> 16;
+                }
+                mm[12] = w[6];
                 hist_from_moments(mm, g.h3, hc);
                 double a = 0.0;
                 for (int c = 0; c < 14; ++c) {
@@ -744,7 +759,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
 // or 4), fixed at compile time so that every line of a pass shares its octant.
 template <int H, int P, int BLOCK, bool INC, int LPD, int BND>
 __global__ void __launch_bounds__(BLOCK) k_persistent(Replica R) {
-    __shared__ PersistShared sh;
+    __shared__ std::conditional_t<INC, PersistSharedInc, PersistShared> sh;
     persistent_body<H, P, BLOCK, INC, LPD, BND>(R, blockIdx.x, sh);
 }
 

@@ -499,6 +499,14 @@ __device__ __forceinline__ uint32_t row_scan(uint32_t v) {
     return v;
 }
 
+// Sum over each group of four lanes of a DPP row, in the group's last lane (lane
+// 4j + 3 ends with lanes 4j .. 4j + 3): two shifted adds.
+__device__ __forceinline__ uint32_t quad_sum(uint32_t v) {
+    v += dpp0<kRowShr1>(v);
+    v += dpp0<kRowShr2>(v);
+    return v;
+}
+
 // position of the r-th (0-based) set bit of m (r < popcount(m)), by halving
 __device__ __forceinline__ int nth_set_bit(uint32_t m, uint32_t r) {
     int pos = 0;
