@@ -56,8 +56,11 @@ namespace spkmc {
 
 // Workgroup-shared state of the persistent kernel for up to DMAX frequency lines
 // (HISTP: with the incremental engine's packed counts of all eight octants; MW:
-// moment words per line, 13 totals, or 32 for the one-round kernels' partial
-// sums of four groups of four lanes, seven packed words and a spare each).
+// moment words per line, 13 totals, or 36 for the one-round kernels' partial
+// sums of four groups of four lanes, seven packed words and a spare each, and
+// four words of padding: the histogram thread of line i reads line i's words as
+// 16-byte loads, and a stride of 32 words would put the lanes of a wavefront on
+// two bank offsets only).
 template <uint32_t DMAX, bool HISTP, int MW>
 struct PersistSharedT {
     double r[14];               // rate table
@@ -86,7 +89,7 @@ struct PersistSharedT {
 };
 // The one-round re-binning kernels, and the incremental engine's (totals kept
 // per line, and every octant's counts).
-using PersistShared = PersistSharedT<kMaxWgDomains, false, 32>;
+using PersistShared = PersistSharedT<kMaxWgDomains, false, 36>;
 using PersistSharedInc = PersistSharedT<kMaxWgDomains, true, 13>;
 // The wide mode (octant edge 16): RND = 2 or 4 rounds of four passes of 32 rows,
 // 256 or 512 lines per workgroup.
