@@ -590,16 +590,32 @@ __device__ __forceinline__ void select_site(const Planes<H> &pl, int cs, uint32_
         // the word holding the target: as many words as have running counts not
         // above its rank; then its rank inside that word
         const uint32_t r0 = j - excl;
-        uint32_t wsel = 0;
+        uint32_t wsel = 0, before = 0, msk = mk[0];
+        if constexpr (WPL == 8) {
+            // the first word whose running count exceeds r0, by halving (the
+            // running counts never decrease)
+            const bool c1 = cum[3] <= r0;
+            const uint32_t a0 = c1 ? cum[4] : cum[0], a1 = c1 ? cum[5] : cum[1], a2 = c1 ? cum[6] : cum[2];
+            const uint32_t m0 = c1 ? mk[4] : mk[0], m1 = c1 ? mk[5] : mk[1], m2 = c1 ? mk[6] : mk[2],
+                           m3 = c1 ? mk[7] : mk[3];
+            before = c1 ? cum[3] : 0u;
+            const bool c2 = a1 <= r0;
+            const uint32_t x0 = c2 ? a2 : a0, n0 = c2 ? m2 : m0, n1 = c2 ? m3 : m1;
+            before = c2 ? a1 : before;
+            const bool c3 = x0 <= r0;
+            msk = c3 ? n1 : n0;
+            before = c3 ? x0 : before;
+            wsel = (c1 ? 4u : 0u) | (c2 ? 2u : 0u) | (c3 ? 1u : 0u);
+        } else {
 #pragma unroll
-        for (int p = 0; p + 1 < WPL; ++p) wsel += cum[p] <= r0 ? 1u : 0u;
-        uint32_t before = 0, msk = mk[0];
+            for (int p = 0; p + 1 < WPL; ++p) wsel += cum[p] <= r0 ? 1u : 0u;
 #pragma unroll
-        for (int p = 1; p < WPL; ++p)
-            if (wsel == (uint32_t)p) {
-                before = cum[p - 1];
-                msk = mk[p];
-            }
+            for (int p = 1; p < WPL; ++p)
+                if (wsel == (uint32_t)p) {
+                    before = cum[p - 1];
+                    msk = mk[p];
+                }
+        }
         const uint32_t q = (uint32_t)(l * WPL) * 32 + wsel * 32 + (uint32_t)nth_set_bit(msk, r0 - before);
         *slot = ((uint32_t)cs << 12) | q;  // after lane 0's store, same wavefront
     }
