@@ -69,6 +69,7 @@ struct PersistSharedT {
     uint32_t histp[HISTP ? DMAX : 1][8][7];  // per domain and octant: packed class counts (incremental engine)
     double acc[DMAX][14];       // per line: running FP64 sums of the frequency line
     double rk[DMAX];
+    double uline[DMAX];         // per line: its event uniform of this cycle (speculative selection -> verification)
     alignas(16) uint32_t zbuf[64][kRowHalo];  // per row: the six halo faces (8 words each), zeros (8)
     uint32_t nbdom[DMAX][6];    // per line: its domain's neighbour domains -x, +x, -y, +y, -z, +z
     uint32_t selq[DMAX];        // per line: (class << 12) | site q of its event, or kNoEvent
@@ -462,7 +463,9 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
             for (int pp = 0; pp < P; ++pp) {
                 const uint32_t ld = (uint32_t)(pp * rows + row);
                 const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
-                const int cs = row_class(sh.acc[ld], ld < nvalid, unit53(ux, uy) * Rspec, l, row);
+                const double u = unit53(ux, uy);
+                if (l == 0) sh.uline[ld] = u;  // kept for the verification
+                const int cs = row_class(sh.acc[ld], ld < nvalid, u * Rspec, l, row);
                 cpred |= (uint32_t)(cs + 1) << (5 * pp);
                 select_site<H>(pl[pp], cs, cs >= 0 ? line_count(ld, cs) : 0u, uz, l, &sh.selq[ld], st);
             }
@@ -554,10 +557,10 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
 #pragma unroll
             for (int pp = 0; pp < P; ++pp) {
                 const uint32_t ld = (uint32_t)(pp * rows + row);
-                const uint32_t ux = bcast_lane(dw.x, pp), uy = bcast_lane(dw.y, pp), uz = bcast_lane(dw.z, pp);
-                const int cs = row_class(sh.acc[ld], ld < nvalid, unit53(ux, uy) * Rmax, l, row);
+                const int cs = row_class(sh.acc[ld], ld < nvalid, sh.uline[ld] * Rmax, l, row);
                 if ((uint32_t)(cs + 1) != ((cpred >> (5 * pp)) & 31u))
-                    select_site<H>(pl[pp], cs, cs >= 0 ? line_count(ld, cs) : 0u, uz, l, &sh.selq[ld], st);
+                    select_site<H>(pl[pp], cs, cs >= 0 ? line_count(ld, cs) : 0u, bcast_lane(dw.z, pp), l,
+                                   &sh.selq[ld], st);
             }
         }
         __syncthreads();
