@@ -148,7 +148,7 @@ __device__ __forceinline__ uint32_t row_lane(uint32_t v, int j) {
 // R_max and derives every round's class planes again from the spins.
 // BND: 1 when the lattice may run with the fixed bound (read from the variant at
 // run time), 0 when it does not (the bound's code is compiled out: present in the
-// loop without running, it still slowed the cycle by about 1.5 %).
+// loop without running, it still slowed the cycle by about 2 %).
 template <int H, int P, int BLOCK, bool INC, int LPD, int BND, int RND = 1,
           class SH = std::conditional_t<INC, PersistSharedInc, PersistShared>>
 __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t gid, SH &sh) {
