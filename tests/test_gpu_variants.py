@@ -148,3 +148,22 @@ def test_variants_in_one_batch(spkmc):
     spkmc.run_batch(batch, 60, obs_every=6)
     for s_, b in zip(solo, batch):
         assert (b.state(), b.records(), b.spins().tobytes()) == s_
+
+
+def test_eight_colour_batch_with_a_bound_member(spkmc):
+    """Eight-colour lattices alone run a batch kernel with one line per domain
+    and the fixed bound's code compiled out; one member with the bound moves the
+    whole batch to the kernel that reads both at run time.  Either way every
+    member ends bit-identical to its solo run."""
+    for specs in ([(64, 16, 0.0, 7, 0), (48, 16, 0.05, 8, 0), (32, 16, -0.05, 9, 0)],
+                  [(64, 16, 0.0, 7, 0), (48, 16, 0.05, 8, BOUND), (32, 16, -0.05, 9, 0)]):
+        print("case eight-colour batch", [s[4] for s in specs], flush=True)
+        solo, batch = [], []
+        for L, d, H, seed, v in specs:
+            a = spkmc.Sim(L, d, H=H, seed=seed, variant=v, record_cap=64)
+            a.run(50, obs_every=5)
+            solo.append((a.state(), a.records(), a.spins().tobytes()))
+            batch.append(spkmc.Sim(L, d, H=H, seed=seed, variant=v, record_cap=64))
+        spkmc.run_batch(batch, 50, obs_every=5)
+        for s_, b in zip(solo, batch):
+            assert (b.state(), b.records(), b.spins().tobytes()) == s_
