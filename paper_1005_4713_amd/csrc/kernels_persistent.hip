@@ -260,6 +260,14 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         prev_colour = s;
 
         Planes<H> pl[P];
+        // lane pp of each row draws for the row's line of pass pp; wavefronts with
+        // no line to histogram draw while the others do (see below)
+        U4 dw{};
+        bool drawn = false;
+        auto draw = [&]() {
+            const uint32_t kd = kbase + (uint32_t)((l < P * RND ? l : 0) * rows + row);
+            dw = philox10((uint32_t)n, (uint32_t)(n >> 32), line_dom(kd), (uint32_t)line_oct(kd, s), g.seed);
+        };
         if constexpr (INC) {
             // --- fold the class changes other workgroups pushed into octant s (and,
             // every kFoldAll cycles, into all octants)
@@ -387,6 +395,10 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
                 }
             }
             __syncthreads();
+            if ((uint32_t)(tid & ~63) >= D) {  // no line of this wavefront to histogram
+                draw();
+                drawn = true;
+            }
             // step 1: histogram and frequency line of every domain of the workgroup,
             // running sums kept for the selection (the same sums in the same order)
             for (uint32_t i = tid; i < D; i += nthr) {
@@ -446,12 +458,7 @@ __device__ __forceinline__ void persistent_body(const Replica &R, const uint32_t
         // other workgroups' maxima travel; once the true R_max is known every row
         // re-derives its class with one ballot and selects again only if the class
         // changed, so the outcome is exactly that of the true R_max.
-        // lane pp of each row draws for the row's line of pass pp
-        U4 dw;
-        {
-            const uint32_t kd = kbase + (uint32_t)((l < P * RND ? l : 0) * rows + row);
-            dw = philox10((uint32_t)n, (uint32_t)(n >> 32), line_dom(kd), (uint32_t)line_oct(kd, s), g.seed);
-        }
+        if (!drawn) draw();
         // sites of class c on line ld
         auto line_count = [&](uint32_t ld, int c) -> uint32_t {
             return INC ? hcount(sh.histp[ld][s], c) : sh.hist[ld][c];
